@@ -1,0 +1,311 @@
+"""ctypes binding of the plain FP64 CPU oracle (ebb_oracle.c).
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, the smoke check and the benchmark's
+CPU-baseline leg import this package; the GPU product path never does.
+
+All arrays are numpy, row-major AoS: X, d, u, v: (nv, 3) float64; tets:
+(nt, 4) int32; B: (nt, 3, 3); V0, mu, lam, E: (nt,); mass: (nv,).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libebboracle.so")
+
+STVK = 0
+NH = 1
+OK = 0
+E_DEGENERATE = -8
+E_INVERTED = -9
+E_NOT_SPD = -10
+E_NOT_CONVERGED = -11
+PRECOND_NONE = 0
+PRECOND_JACOBI = 1
+
+_lib = None
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        from . import build as _b
+        _b.build()
+    lib = C.CDLL(_LIB_PATH)
+    P = C.c_void_p
+    I64 = C.c_int64
+    D = C.c_double
+    I32 = C.c_int32
+    lib.orc_lame.argtypes = [D, D, P, P]
+    lib.orc_precompute.argtypes = [I64, I64, P, P, D, P, D, P, P, P, P, P, P]
+    for name in ("orc_stress",):
+        getattr(lib, name).argtypes = [C.c_int, D, D, P, P]
+    lib.orc_dstress.argtypes = [C.c_int, D, D, P, P, P]
+    lib.orc_d2stress.argtypes = [C.c_int, D, D, P, P, P, P]
+    lib.orc_energy_density.argtypes = [C.c_int, D, D, P, P]
+    base = [C.c_int, I64, I64, P, P, P, P, P]
+    lib.orc_forces.argtypes = base + [P, P]
+    lib.orc_kmul.argtypes = base + [P, P, P]
+    lib.orc_tmul.argtypes = base + [P, P, P, P]
+    lib.orc_energy.argtypes = base + [P, P]
+    lib.orc_jacobi_diag.argtypes = base + [P, D, P, P]
+    lib.orc_implicit_step.argtypes = base + [P, P, D, P, D, I32, I32, P, P, P, P]
+    lib.orc_step_vjp.argtypes = base + [P, P, P, D, D, I32, I32, P, P, P, P, P, P, P, P]
+    lib.orc_group_by.argtypes = [I64, I64, P, P, P]
+    lib.orc_morton.argtypes = [I64, I64, P, P, P, P, P]
+    for f in ("orc_precompute", "orc_stress", "orc_dstress", "orc_d2stress",
+              "orc_energy_density", "orc_forces", "orc_kmul", "orc_tmul", "orc_energy",
+              "orc_jacobi_diag", "orc_implicit_step", "orc_step_vjp", "orc_group_by",
+              "orc_morton"):
+        getattr(lib, f).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _f64(a, shape=None) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def lame(E: float, nu: float):
+    mu = C.c_double()
+    lam = C.c_double()
+    _load().orc_lame(E, nu, C.byref(mu), C.byref(lam))
+    return mu.value, lam.value
+
+
+def _chk(st: int, what: str, allow=(OK,)):
+    if st not in allow:
+        raise OracleError(st, what)
+    return st
+
+
+def stress(model, mu, lam, G):
+    G = _f64(G, (3, 3))
+    P = np.zeros((3, 3))
+    _chk(_load().orc_stress(model, mu, lam, _p(G), _p(P)), "stress")
+    return P
+
+
+def dstress(model, mu, lam, G, dF):
+    G = _f64(G, (3, 3))
+    dF = _f64(dF, (3, 3))
+    dP = np.zeros((3, 3))
+    _chk(_load().orc_dstress(model, mu, lam, _p(G), _p(dF), _p(dP)), "dstress")
+    return dP
+
+
+def d2stress(model, mu, lam, G, A, W):
+    G, A, W = _f64(G, (3, 3)), _f64(A, (3, 3)), _f64(W, (3, 3))
+    Q = np.zeros((3, 3))
+    _chk(_load().orc_d2stress(model, mu, lam, _p(G), _p(A), _p(W), _p(Q)), "d2stress")
+    return Q
+
+
+def energy_density(model, mu, lam, G):
+    G = _f64(G, (3, 3))
+    psi = C.c_double()
+    _chk(_load().orc_energy_density(model, mu, lam, _p(G), C.byref(psi)), "energy_density")
+    return psi.value
+
+
+def group_by(nv: int, tets: np.ndarray):
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    nt = tets.shape[0]
+    row_ptr = np.zeros(nv + 1, dtype=np.int64)
+    inc = np.zeros(4 * nt, dtype=np.int32)
+    _chk(_load().orc_group_by(nv, nt, _p(tets), _p(row_ptr), _p(inc)), "group_by")
+    return row_ptr, inc
+
+
+def morton(X: np.ndarray, tets: np.ndarray):
+    X = _f64(X)
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    nv, nt = X.shape[0], tets.shape[0]
+    codes = np.zeros(nv, dtype=np.uint64)
+    vperm = np.zeros(nv, dtype=np.int32)
+    tperm = np.zeros(nt, dtype=np.int32)
+    _chk(_load().orc_morton(nv, nt, _p(X), _p(tets), _p(codes), _p(vperm), _p(tperm)), "morton")
+    return codes, vperm, tperm
+
+
+@dataclass
+class FEM:
+    """Rest-shape data of one mesh plus the material, as the oracle sees it."""
+    model: int
+    tets: np.ndarray
+    B: np.ndarray
+    V0: np.ndarray
+    mu: np.ndarray
+    lam: np.ndarray
+    E: np.ndarray
+    mass: np.ndarray
+    pinned: np.ndarray
+    nu: float
+
+    @property
+    def nv(self):
+        return self.mass.shape[0]
+
+    @property
+    def nt(self):
+        return self.tets.shape[0]
+
+    @classmethod
+    def create(cls, model, X, tets, E, nu, rho=1000.0, pinned=None):
+        X = _f64(X)
+        tets = np.ascontiguousarray(tets, dtype=np.int32)
+        nv, nt = X.shape[0], tets.shape[0]
+        Et = _f64(np.broadcast_to(np.asarray(E, dtype=np.float64), (nt,)))
+        B = np.zeros((nt, 3, 3))
+        V0 = np.zeros(nt)
+        mu = np.zeros(nt)
+        lam = np.zeros(nt)
+        mass = np.zeros(nv)
+        bad = C.c_int64(-1)
+        st = _load().orc_precompute(nv, nt, _p(X), _p(tets), rho, _p(Et), nu, _p(B), _p(V0),
+                                    _p(mu), _p(lam), _p(mass), C.byref(bad))
+        _chk(st, f"precompute (tet {bad.value})")
+        if pinned is None:
+            pinned = np.zeros(nv, dtype=np.uint8)
+        pinned = np.ascontiguousarray(pinned, dtype=np.uint8)
+        return cls(model, tets, B, V0, mu, lam, Et, mass, pinned, nu)
+
+    def _base(self):
+        return [self.model, self.nv, self.nt, _p(self.tets), _p(self.B), _p(self.V0),
+                _p(self.mu), _p(self.lam)]
+
+    def forces(self, d):
+        d = _f64(d, (self.nv, 3))
+        f = np.zeros((self.nv, 3))
+        _chk(_load().orc_forces(*self._base(), _p(d), _p(f)), "forces")
+        return f
+
+    def kmul(self, d, u):
+        d = _f64(d, (self.nv, 3))
+        u = _f64(u, (self.nv, 3))
+        y = np.zeros((self.nv, 3))
+        _chk(_load().orc_kmul(*self._base(), _p(d), _p(u), _p(y)), "kmul")
+        return y
+
+    def tmul(self, d, a, w):
+        d, a, w = (_f64(x, (self.nv, 3)) for x in (d, a, w))
+        out = np.zeros((self.nv, 3))
+        _chk(_load().orc_tmul(*self._base(), _p(d), _p(a), _p(w), _p(out)), "tmul")
+        return out
+
+    def energy(self, d):
+        d = _f64(d, (self.nv, 3))
+        W = C.c_double()
+        _chk(_load().orc_energy(*self._base(), _p(d), C.byref(W)), "energy")
+        return W.value
+
+    def jacobi_diag(self, d, dt):
+        d = _f64(d, (self.nv, 3))
+        diag = np.zeros((self.nv, 3))
+        _chk(_load().orc_jacobi_diag(*self._base(), _p(self.mass), dt, _p(d), _p(diag)),
+             "jacobi_diag")
+        return diag
+
+    def implicit_step(self, d, v, dt, g=(0.0, 0.0, -9.81), tol=0.0, maxit=100,
+                      precond=PRECOND_JACOBI, allow_not_converged=True):
+        """Returns (d', v', dv, stats) without touching the inputs."""
+        d = _f64(d, (self.nv, 3)).copy()
+        v = _f64(v, (self.nv, 3)).copy()
+        g = _f64(g)
+        dv = np.zeros((self.nv, 3))
+        st = Stats()
+        rc = _load().orc_implicit_step(*self._base(), _p(self.mass), _p(self.pinned), dt, _p(g),
+                                       tol, maxit, precond, _p(d), _p(v), _p(dv), C.byref(st))
+        allow = (OK, E_NOT_CONVERGED) if allow_not_converged else (OK,)
+        _chk(rc, "implicit_step", allow)
+        return d, v, dv, st
+
+    def step_vjp(self, d_n, v_np1, gx, gv, dt, tol=1e-12, maxit=10000,
+                 precond=PRECOND_JACOBI):
+        """Returns (d_bar, v_bar, E_bar, stats) of one implicit step."""
+        d_n, v_np1, gx, gv = (_f64(x, (self.nv, 3)) for x in (d_n, v_np1, gx, gv))
+        d_bar = np.zeros((self.nv, 3))
+        v_bar = np.zeros((self.nv, 3))
+        E_bar = np.zeros(self.nt)
+        st = Stats()
+        rc = _load().orc_step_vjp(*self._base(), _p(self.E), _p(self.mass), _p(self.pinned),
+                                  dt, tol, maxit, precond, _p(d_n), _p(v_np1), _p(gx), _p(gv),
+                                  _p(d_bar), _p(v_bar), _p(E_bar), C.byref(st))
+        _chk(rc, "step_vjp", (OK, E_NOT_CONVERGED))
+        return d_bar, v_bar, E_bar, st
+
+
+def trajectory(fem: FEM, d0, v0, steps, dt, tol, maxit, g=(0.0, 0.0, -9.81),
+               precond=PRECOND_JACOBI):
+    """Run `steps` implicit steps; returns the list of (d, v) states 0..steps."""
+    states = [(np.array(d0, dtype=np.float64), np.array(v0, dtype=np.float64))]
+    d, v = states[0]
+    for _ in range(steps):
+        d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit, precond=precond)
+        states.append((d, v))
+    return states
+
+
+def trajectory_grad(fem: FEM, d0, v0, steps, dt, tol, maxit, target, X,
+                    g=(0.0, 0.0, -9.81), precond=PRECOND_JACOBI, checkpoint_every=0):
+    """Loss L = ||x_T - target||^2 with x = X + d; returns (L, dL/dd0, dL/dE).
+
+    checkpoint_every = k > 0 keeps only every k-th state and recomputes each
+    segment forward before reversing it; 0 keeps every state.
+    """
+    k = checkpoint_every if checkpoint_every > 0 else steps
+    ckpt = {0: (np.array(d0, dtype=np.float64), np.array(v0, dtype=np.float64))}
+    d, v = ckpt[0]
+    for n in range(steps):
+        d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit, precond=precond)
+        if (n + 1) % k == 0 and n + 1 < steps:
+            ckpt[n + 1] = (d, v)
+    xT = X + d
+    L = float(np.sum((xT - target) ** 2))
+    gx = 2.0 * (xT - target)
+    gv = np.zeros_like(gx)
+    E_bar = np.zeros(fem.nt)
+    seg_starts = sorted(ckpt.keys(), reverse=True)
+    end = steps
+    for s0 in seg_starts:
+        # recompute the states of this segment
+        states = [ckpt[s0]]
+        d, v = ckpt[s0]
+        for _ in range(s0, end - 1):
+            d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit,
+                                               precond=precond)
+            states.append((d, v))
+        # reverse the steps s0 .. end-1; step n maps states[n-s0] -> n+1
+        for n in range(end - 1, s0 - 1, -1):
+            d_n, v_n = states[n - s0]
+            _d1, v_np1, _dv, _st = fem.implicit_step(d_n, v_n, dt, g=g, tol=tol, maxit=maxit,
+                                                     precond=precond)
+            d_bar, v_bar, eb, _ = fem.step_vjp(d_n, v_np1, gx, gv, dt, tol=tol, maxit=maxit,
+                                               precond=precond)
+            E_bar += eb
+            gx, gv = d_bar, v_bar
+        end = s0
+    return L, gx, E_bar
