@@ -1,0 +1,269 @@
+/* ebbx.h -- C-ABI of the MI355X (gfx950) tet-FEM element map.
+ *
+ * The calls follow the relational model of Ebb (Bernstein et al., "Ebb: A
+ * DSL for Physical Simulation on CPUs and GPUs"): relations are tables,
+ * fields are column-stored arrays over a relation, key-fields map rows of one
+ * relation to rows of another, and grouping a relation by a key-field builds
+ * the inverted index that query-loops read (Developing Domain Libraries,
+ * "Relational Modeling Primitives"; Runtime Implementation).  Calls execute
+ * immediately, like the paper's OpenGL-style runtime API.
+ *
+ * On top of the relations sits the tet-FEM domain of the paper's Vega and
+ * FreeFem++ workloads (Developing Domain Libraries, "Example: FEM tetmesh";
+ * Performance Evaluation): displacement, velocity and force on vertices,
+ * material on tets, hyperelastic internal forces, the stiffness product and
+ * an implicit backward-Euler step solved with (Jacobi-)preconditioned CG.
+ *
+ * Conventions shared by every call:
+ *  - Return value: EBBX_OK (0) or a negative ebbx_status.  A failed call has
+ *    no side effect and sets any output handle to NULL; ebbx_last_error()
+ *    returns a thread-local message for the last failure.  No C++ exception
+ *    crosses this boundary.
+ *  - Memory: every pointer argument named *_dev (and every vector argument of
+ *    the compute calls) is device memory on the GPU the library runs on.
+ *    Bound fields are borrowed: the caller owns them and keeps them alive
+ *    while a relation or FEM object that uses them exists.  Hidden fields
+ *    (B = Dm^-1, V0, mass, incidence, scratch, solver vectors) are owned by
+ *    the library, allocated through the allocator hook (default hipMalloc)
+ *    and released by the matching *_destroy call.
+ *  - Layout: column store ("struct of arrays").  A field of ncomp components
+ *    over a relation of size n is ncomp contiguous columns of n elements
+ *    (a C-contiguous array of shape (ncomp, n)).  Vertex vectors d, u, v, f,
+ *    y are FP64 (3, nv).
+ *  - Streams: ebbx_stream is a hipStream_t (NULL = the null stream).  Setup
+ *    calls (create, bind, group, reorder, fem_create) are synchronous.  Compute
+ *    calls enqueue on the given stream and return without synchronising;
+ *    conditions found on the device (inverted element, CG breakdown, no
+ *    convergence) are reported in device-side stats read by ebbx_stats_fetch.
+ *  - Threads: calls on different objects may come from different threads;
+ *    calls on one object must not overlap.
+ */
+#ifndef EBBX_H
+#define EBBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ebbx_status;
+enum {
+    EBBX_OK = 0,
+    EBBX_E_ARG = -1,          /* null handle, bad enum, bad size */
+    EBBX_E_DTYPE = -2,        /* field has the wrong element type */
+    EBBX_E_SHAPE = -3,        /* field has the wrong component count */
+    EBBX_E_LAYOUT = -4,       /* pointer misaligned for its type */
+    EBBX_E_KEY_RANGE = -5,    /* a key is outside [0, size of target) */
+    EBBX_E_PHASE = -6,        /* an output aliases an input of the same call */
+    EBBX_E_NOT_GROUPED = -7,  /* the call needs a grouping that was not built */
+    EBBX_E_DEGENERATE = -8,   /* a rest tet has V0 <= 0 */
+    EBBX_E_INVERTED = -9,     /* a deformed neo-Hookean tet has J <= 0 */
+    EBBX_E_NOT_SPD = -10,     /* CG met p^T A p <= 0 */
+    EBBX_E_NOT_CONVERGED = -11, /* CG reached maxit before tol (iterate kept) */
+    EBBX_E_HIP = -12,         /* a HIP runtime call failed */
+    EBBX_E_OOM = -13,         /* allocation failed */
+    EBBX_E_STATE = -14,       /* object used in a state that forbids the call */
+    EBBX_E_NOT_FOUND = -15    /* no field or key-field of that name */
+};
+
+typedef enum { EBBX_F32 = 0, EBBX_F64 = 1, EBBX_I32 = 2, EBBX_U8 = 3, EBBX_I64 = 4 } ebbx_dtype;
+typedef struct ebbx_relation_s *ebbx_relation;
+typedef struct ebbx_fem_s *ebbx_fem;
+typedef void *ebbx_stream;   /* hipStream_t */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ebbx_last_error(void);
+
+/* Library version, e.g. 100 for 0.1.0. */
+int32_t ebbx_version(void);
+
+/* Allocator hook for hidden fields.  alloc(bytes, ctx, stream) returns device
+ * memory or NULL; free(ptr, ctx) releases it.  Passing alloc = NULL restores
+ * hipMalloc/hipFree.  Objects keep the hook that was current when they were
+ * created and release their memory through it. */
+ebbx_status ebbx_set_allocator(void *(*alloc)(size_t bytes, void *ctx, ebbx_stream stream),
+                               void (*free_fn)(void *ptr, void *ctx), void *ctx);
+
+/* ---- relations, fields, key-fields (Developing Domain Libraries) -------- */
+
+/* A relation (table) of `size` rows; `name` is copied. */
+ebbx_status ebbx_relation_create(const char *name, int64_t size, ebbx_relation *out);
+ebbx_status ebbx_relation_destroy(ebbx_relation rel);
+ebbx_status ebbx_relation_size(ebbx_relation rel, int64_t *out);
+
+/* Bind caller-owned column-store memory (ncomp, size) of type dtype as field
+ * `name` (a zero-copy view, as the paper's interoperation with external
+ * libraries allows).  Rebinding a name replaces the view.  EBBX_E_LAYOUT if
+ * dev_ptr is not aligned to its element size. */
+ebbx_status ebbx_field_bind(ebbx_relation rel, const char *name, ebbx_dtype dtype,
+                            int32_t ncomp, void *dev_ptr);
+
+/* Bind a key-field: `arity` int32 keys per row of rel, column store
+ * (arity, size), each referring to a row of `target` (e.g. tets.v[4] ->
+ * verts).  Validates on the device that every key is in [0, size(target)),
+ * returning EBBX_E_KEY_RANGE otherwise (the paper's guarantee that key
+ * accesses stay in bounds by construction).  Synchronous. */
+ebbx_status ebbx_keyfield_bind(ebbx_relation rel, const char *name, ebbx_relation target,
+                               int32_t arity, int32_t *dev_ptr);
+
+/* Group rel by key-field `keyfield` (Runtime Implementation, "Relational
+ * Primitives Implementations"): builds on the target relation the hidden
+ * index of the (row, slot) incidences of rel whose key equals each target
+ * row -- CSR with row_ptr (size(target)+1, int64) and entries 4*row+slot
+ * (for arity 4; in general arity*row+slot, int32), each target row's entries
+ * in increasing order.  Deterministic and bit-exact.  Synchronous. */
+ebbx_status ebbx_relation_group_by(ebbx_relation rel, const char *keyfield);
+
+/* Copy the grouping built by ebbx_relation_group_by into caller buffers:
+ * row_ptr_dev (size(target)+1 int64), inc_dev (arity*size(rel) int32).
+ * EBBX_E_NOT_GROUPED if the grouping does not exist.  Synchronous. */
+ebbx_status ebbx_group_export(ebbx_relation rel, const char *keyfield, int64_t *row_ptr_dev,
+                              int32_t *inc_dev);
+
+/* Morton (Z-order) locality order, which the opaque-key model lets the
+ * runtime choose (Developing Domain Libraries: keys are opaque, so the
+ * runtime may reorder relations).  From the FP64 (3, nv) field `pos_field`
+ * of verts: per-axis bounding box [lo, hi], q = min(2^21-1, floor((x-lo) *
+ * (2^21/(hi-lo)))) (q = 0 on a flat axis), bit b of q_x, q_y, q_z at bits
+ * 3b, 3b+1, 3b+2 of a uint64 code; vertices sorted by (code, old id).  Rows
+ * of rel are then sorted by (min over slots of the new vertex id of key-field
+ * `keyfield`, old row).  Outputs (device, nullable): codes_dev[nv] (uint64),
+ * vperm_dev[nv] and tperm_dev[size(rel)], each mapping new -> old.  Nothing
+ * is permuted.  Synchronous. */
+ebbx_status ebbx_morton_order(ebbx_relation verts, const char *pos_field, ebbx_relation rel,
+                              const char *keyfield, uint64_t *codes_dev, int32_t *vperm_dev,
+                              int32_t *tperm_dev);
+
+/* Permute rel in place by new_to_old_dev (a permutation of [0, size)): every
+ * bound field and key-field of rel is gathered row-wise, and every key-field
+ * of any live relation that targets rel is remapped through the inverse.
+ * Groupings involving rel are dropped.  Synchronous. */
+ebbx_status ebbx_relation_reorder(ebbx_relation rel, const int32_t *new_to_old_dev);
+
+/* ---- the tet-FEM domain -------------------------------------------------- */
+
+enum { EBBX_STVK = 0, EBBX_NH = 1 };
+/* Scatter-reduce of per-tet results into vertex fields:
+ *   ATOMIC: FP64 hardware atomics, one per (tet, corner, component);
+ *   SEG:    per-corner partials, then a vertex-owned sum over the grouping's
+ *           incidence in fixed order (bitwise deterministic);
+ *   BLOCK:  tets processed in blocks that stage their vertices in LDS and
+ *           pre-reduce there; vertices whose incident tets all lie in the
+ *           block are stored, the rest added atomically;
+ *   AUTO:   the library's choice (the autotuner's, if it ran). */
+enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3 };
+
+typedef struct {
+    int32_t model;       /* EBBX_STVK or EBBX_NH */
+    int32_t elem_prec;   /* EBBX_F32 or EBBX_F64: per-tet arithmetic and storage */
+    double rho;          /* density, > 0 */
+    double E;            /* Young's modulus (ignored if E_field is set) */
+    double nu;           /* Poisson's ratio, in (-1, 0.5) */
+    const char *E_field; /* nullable: FP64 (1, nt) per-tet Young's modulus on tets */
+    int32_t strategy;    /* EBBX_STRAT_* */
+    int32_t block;       /* threads per block for the element kernels, 0 = default */
+} ebbx_fem_params;
+
+/* Build the FEM domain over `tets` (key-field `keyfield`, arity 4, target
+ * `verts`) with rest positions `pos_field` (FP64 (3, nv) on verts) and an
+ * optional U8 (1, nv) `pinned_field` (nonzero = Dirichlet vertex).  Computes
+ * per tet Dm = [X1-X0 | X2-X0 | X3-X0], V0 = det(Dm)/6 and B = Dm^-1, the Lame
+ * parameters mu = E/(2(1+nu)), lam = E nu/((1+nu)(1-2nu)), and the lumped mass
+ * m_v = sum of rho V0/4 over incident tets.  EBBX_E_DEGENERATE if a tet has
+ * V0 <= 0.  Groups tets by keyfield if not yet grouped.  The FEM keeps views
+ * of the key-field and the pinned field.  Synchronous. */
+ebbx_status ebbx_fem_create(ebbx_relation tets, const char *keyfield, ebbx_relation verts,
+                            const char *pos_field, const char *pinned_field,
+                            const ebbx_fem_params *params, ebbx_fem *out);
+ebbx_status ebbx_fem_destroy(ebbx_fem fem);
+
+/* Change the scatter strategy and block size of an existing FEM. */
+ebbx_status ebbx_fem_set_strategy(ebbx_fem fem, int32_t strategy, int32_t block);
+/* Read back the strategy and block size in use (after AUTO resolution). */
+ebbx_status ebbx_fem_get_strategy(ebbx_fem fem, int32_t *strategy, int32_t *block);
+
+/* Internal elastic force at displacement d (x = X + d): per tet G = dD B with
+ * dD = [d1-d0 | d2-d0 | d3-d0], F = I + G, first Piola-Kirchhoff stress P(F)
+ * (StVK: P = F (2 mu E + lam tr(E) I), E = (G + G^T + G^T G)/2; NH: P =
+ * mu (F - F^-T) + lam ln(J) F^-T), H = -V0 P B^T; columns of H go to corners
+ * 1..3 and minus their sum to corner 0, reduced (+=) into f (Vega and
+ * FreeFem++ workloads).  accumulate = 0 overwrites f, 1 adds to it (a reduce
+ * phase field).  No gravity.  EBBX_E_PHASE if f aliases d.  An NH tet with
+ * J <= 0 is counted in the FEM's device status (ebbx_fem_status). */
+ebbx_status ebbx_fem_forces(ebbx_fem fem, const double *d, double *f, int32_t accumulate,
+                            ebbx_stream stream);
+
+/* Stiffness product y (+)= K u with K = df/dx at displacement d, evaluated
+ * matrix-free per tet through dF = dU B and the directional derivative of P:
+ * StVK dP = dF S + F (2 mu dE + lam tr(dE) I), dE = sym(F^T dF); NH dP =
+ * mu dF + (mu - lam ln J) F^-T dF^T F^-T + lam (F^-T : dF) F^-T; then
+ * dH = -V0 dP B^T scattered as in ebbx_fem_forces.  No mass, no mask.
+ * EBBX_E_PHASE if y aliases d or u. */
+ebbx_status ebbx_fem_Kmul(ebbx_fem fem, const double *d, const double *u, double *y,
+                          int32_t accumulate, ebbx_stream stream);
+
+/* Total strain energy W = sum V0 psi(F) into out_dev[0] (FP64):
+ * StVK psi = mu E:E + lam tr(E)^2/2; NH psi = mu (tr(F^T F) - 3)/2 - mu ln J
+ * + lam (ln J)^2/2. */
+ebbx_status ebbx_fem_energy(ebbx_fem fem, const double *d, double *out_dev, ebbx_stream stream);
+
+/* Jacobi diagonal of A = M - dt^2 K(d): diag[c][v] = m_v - dt^2 K[(v,c),(v,c)],
+ * computed matrix-free from the 12 per-tet diagonal entries
+ * -V0 dP(e_c b_a^T) : (e_c b_a^T), b_a the shape-function gradient of corner a
+ * (rows of B for a = 1..3, minus their sum for a = 0).  FP64 (3, nv). */
+ebbx_status ebbx_fem_jacobi_diag(ebbx_fem fem, const double *d, double dt, double *diag,
+                                 ebbx_stream stream);
+
+/* Copy the lumped mass (nv FP64) into mass_dev. */
+ebbx_status ebbx_fem_mass(ebbx_fem fem, double *mass_dev, ebbx_stream stream);
+
+/* Count of inverted NH tets seen by force/stiffness calls since the last
+ * reset (reset = 1 clears it after reading).  Synchronises the stream. */
+ebbx_status ebbx_fem_status(ebbx_fem fem, int64_t *n_inverted, int32_t reset, ebbx_stream stream);
+
+enum { EBBX_PRECOND_NONE = 0, EBBX_PRECOND_JACOBI = 1 };
+
+typedef struct {
+    double dt;        /* time step, > 0 */
+    double g[3];      /* body acceleration, e.g. (0, 0, -9.81) */
+    double tol;       /* stop when ||r|| <= tol ||Pi b||; 0 runs exactly maxit iterations */
+    int32_t maxit;    /* iteration cap, >= 0 */
+    int32_t precond;  /* EBBX_PRECOND_* */
+} ebbx_step_params;
+
+/* Solver report, written to device memory by ebbx_implicit_step. */
+typedef struct {
+    int32_t iters;        /* CG iterations run */
+    int32_t status;       /* EBBX_OK, EBBX_E_NOT_SPD, EBBX_E_NOT_CONVERGED, EBBX_E_INVERTED */
+    double rel_res;       /* ||r|| / ||Pi b|| at exit (0 if Pi b = 0) */
+    int64_t n_inverted;   /* NH tets with J <= 0 at d_n */
+} ebbx_step_stats;
+
+/* One linearised backward-Euler step (Vega workload; Performance Evaluation):
+ *   A = M - dt^2 K(d),  b = dt (f(d) + M g + dt K(d) v),
+ *   Pi zeroes pinned rows; masked PCG from dv = 0 on A dv = Pi b with
+ *   alpha = r^T z / p^T A p, beta = r_new^T z_new / r^T z, z = D^-1 r (Jacobi)
+ *   or z = r; stop when ||r|| <= tol ||Pi b|| or after maxit iterations;
+ *   then v += dv, d += dt v.
+ * d and v are FP64 (3, nv), updated in place.  CG scalars and dot products
+ * stay in FP64 on the device; the iterations run as one captured HIP graph
+ * (no host synchronisation).  stats_dev (device, nullable) receives the
+ * report.  If the solve breaks down (p^T A p <= 0) d and v are left
+ * unchanged.  EBBX_E_PHASE if d and v alias. */
+ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
+                               ebbx_step_stats *stats_dev, ebbx_stream stream);
+
+/* Copy a device stats record to the host; synchronises the stream. */
+ebbx_status ebbx_stats_fetch(const ebbx_step_stats *stats_dev, ebbx_step_stats *host,
+                             ebbx_stream stream);
+
+/* Stream `bytes` through a library-owned buffer to evict device caches
+ * (including the memory-side Infinity Cache) before a cold measurement. */
+ebbx_status ebbx_cache_flush(size_t bytes, ebbx_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBBX_H */

@@ -1,0 +1,370 @@
+"""Thin ctypes binding of libebbx.so (the C-ABI in include/ebbx.h).
+
+Argument marshalling only: every step runs in the HIP library.  PyTorch
+supplies device memory (tensors are passed as raw pointers; the library's
+hidden fields come from torch's caching allocator through the allocator
+hook) and streams.  Importing this module does not load the library; the
+first call does, and raises if libebbx.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libebbx.so")
+
+OK = 0
+E_ARG, E_DTYPE, E_SHAPE, E_LAYOUT, E_KEY_RANGE, E_PHASE, E_NOT_GROUPED = -1, -2, -3, -4, -5, -6, -7
+E_DEGENERATE, E_INVERTED, E_NOT_SPD, E_NOT_CONVERGED, E_HIP, E_OOM, E_STATE, E_NOT_FOUND = (
+    -8, -9, -10, -11, -12, -13, -14, -15)
+F32, F64, I32, U8, I64 = 0, 1, 2, 3, 4
+STVK, NH = 0, 1
+STRAT_AUTO, STRAT_ATOMIC, STRAT_SEG, STRAT_BLOCK = 0, 1, 2, 3
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
+
+_DT = {torch.float32: F32, torch.float64: F64, torch.int32: I32, torch.uint8: U8, torch.int64: I64}
+
+
+class EbbxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ebbx status {code}: {msg}")
+        self.code = code
+
+
+class FemParams(C.Structure):
+    _fields_ = [("model", C.c_int32), ("elem_prec", C.c_int32), ("rho", C.c_double), ("E", C.c_double),
+                ("nu", C.c_double), ("E_field", C.c_char_p), ("strategy", C.c_int32), ("block", C.c_int32)]
+
+
+class StepParams(C.Structure):
+    _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("tol", C.c_double), ("maxit", C.c_int32),
+                ("precond", C.c_int32)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
+                ("n_inverted", C.c_int64)]
+
+
+_lib = None
+_ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+_FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_hooks = []
+
+
+def _torch_alloc(nbytes, _ctx, stream):
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), stream=stream or None)
+    except Exception:   # out of memory: the library reports EBBX_E_OOM
+        return None
+
+
+def _torch_free(ptr, _ctx):
+    torch.cuda.caching_allocator_delete(ptr)
+
+
+def lib():
+    """Load libebbx.so (once).  Raises if it was not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(the GPU path has no fallback)")
+    L = C.CDLL(LIB_PATH)
+    P, I32_, I64_, D, S = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_char_p
+    sig = {
+        "ebbx_last_error": ([], C.c_char_p),
+        "ebbx_version": ([], C.c_int32),
+        "ebbx_set_allocator": ([_ALLOC_T, _FREE_T, P], I32_),
+        "ebbx_relation_create": ([S, I64_, C.POINTER(P)], I32_),
+        "ebbx_relation_destroy": ([P], I32_),
+        "ebbx_relation_size": ([P, C.POINTER(I64_)], I32_),
+        "ebbx_field_bind": ([P, S, C.c_int, I32_, P], I32_),
+        "ebbx_keyfield_bind": ([P, S, P, I32_, P], I32_),
+        "ebbx_relation_group_by": ([P, S], I32_),
+        "ebbx_group_export": ([P, S, P, P], I32_),
+        "ebbx_morton_order": ([P, S, P, S, P, P, P], I32_),
+        "ebbx_relation_reorder": ([P, P], I32_),
+        "ebbx_fem_create": ([P, S, P, S, S, C.POINTER(FemParams), C.POINTER(P)], I32_),
+        "ebbx_fem_destroy": ([P], I32_),
+        "ebbx_fem_set_strategy": ([P, I32_, I32_], I32_),
+        "ebbx_fem_get_strategy": ([P, C.POINTER(I32_), C.POINTER(I32_)], I32_),
+        "ebbx_fem_forces": ([P, P, P, I32_, P], I32_),
+        "ebbx_fem_Kmul": ([P, P, P, P, I32_, P], I32_),
+        "ebbx_fem_energy": ([P, P, P, P], I32_),
+        "ebbx_fem_jacobi_diag": ([P, P, D, P, P], I32_),
+        "ebbx_fem_mass": ([P, P, P], I32_),
+        "ebbx_fem_status": ([P, C.POINTER(I64_), I32_, P], I32_),
+        "ebbx_implicit_step": ([P, P, P, C.POINTER(StepParams), P, P], I32_),
+        "ebbx_stats_fetch": ([P, C.POINTER(StepStats), P], I32_),
+        "ebbx_cache_flush": ([C.c_size_t, P], I32_),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    use_torch_allocator(True)
+    return L
+
+
+def use_torch_allocator(on: bool = True):
+    """Route the library's hidden-field allocations through torch's caching allocator."""
+    L = lib()
+    if on:
+        a, f = _ALLOC_T(_torch_alloc), _FREE_T(_torch_free)
+        _hooks[:] = [a, f]
+        _check(L.ebbx_set_allocator(a, f, None))
+    else:
+        _check(L.ebbx_set_allocator(_ALLOC_T(), _FREE_T(), None))
+
+
+def _check(st):
+    if st != OK:
+        raise EbbxError(st, lib().ebbx_last_error().decode(errors="replace"))
+    return st
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream) -> C.c_void_p:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _dev(t: torch.Tensor, dtype, what) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{what}: expected a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what}: tensor must be contiguous (column store)")
+    return t
+
+
+class Relation:
+    """A relation (table).  Bound tensors are kept alive by this object."""
+
+    def __init__(self, name: str, size: int):
+        h = C.c_void_p()
+        _check(lib().ebbx_relation_create(name.encode(), int(size), C.byref(h)))
+        self.h = h
+        self.name = name
+        self.size = int(size)
+        self._keep = {}
+
+    def bind_field(self, name: str, t: torch.Tensor):
+        """t: (ncomp, size) or (size,) CUDA tensor, column store."""
+        if t.dtype not in _DT:
+            raise TypeError(f"unsupported dtype {t.dtype}")
+        ncomp = 1 if t.dim() == 1 else t.shape[0]
+        if t.shape[-1] != self.size:
+            raise ValueError(f"field {name}: last dim {t.shape[-1]} != relation size {self.size}")
+        _dev(t, t.dtype, name)
+        _check(lib().ebbx_field_bind(self.h, name.encode(), _DT[t.dtype], int(ncomp), _ptr(t)))
+        self._keep[name] = t
+
+    def bind_keyfield(self, name: str, target: "Relation", t: torch.Tensor):
+        """t: (arity, size) int32 CUDA tensor of keys into target."""
+        _dev(t, torch.int32, name)
+        arity = 1 if t.dim() == 1 else t.shape[0]
+        if t.shape[-1] != self.size:
+            raise ValueError(f"key-field {name}: last dim {t.shape[-1]} != relation size {self.size}")
+        _check(lib().ebbx_keyfield_bind(self.h, name.encode(), target.h, int(arity), _ptr(t)))
+        self._keep[name] = t
+        self._keep["__target_" + name] = target
+
+    def group_by(self, keyfield: str):
+        _check(lib().ebbx_relation_group_by(self.h, keyfield.encode()))
+
+    def group_export(self, keyfield: str, n_target: int, arity: int):
+        rp = torch.empty(n_target + 1, dtype=torch.int64, device="cuda")
+        inc = torch.empty(max(arity * self.size, 1), dtype=torch.int32, device="cuda")
+        _check(lib().ebbx_group_export(self.h, keyfield.encode(), _ptr(rp), _ptr(inc)))
+        return rp, inc[: arity * self.size]
+
+    def reorder(self, new_to_old: torch.Tensor):
+        _dev(new_to_old, torch.int32, "permutation")
+        _check(lib().ebbx_relation_reorder(self.h, _ptr(new_to_old)))
+
+    def close(self):
+        if self.h:
+            _check(lib().ebbx_relation_destroy(self.h))
+            self.h = None
+
+
+def morton_order(verts: Relation, pos_field: str, rel: Relation, keyfield: str):
+    """Returns (codes uint64-as-int64, vperm int32, tperm int32), each new -> old."""
+    codes = torch.empty(max(verts.size, 1), dtype=torch.int64, device="cuda")
+    vperm = torch.empty(max(verts.size, 1), dtype=torch.int32, device="cuda")
+    tperm = torch.empty(max(rel.size, 1), dtype=torch.int32, device="cuda")
+    _check(lib().ebbx_morton_order(verts.h, pos_field.encode(), rel.h, keyfield.encode(), _ptr(codes),
+                                   _ptr(vperm), _ptr(tperm)))
+    return codes[: verts.size], vperm[: verts.size], tperm[: rel.size]
+
+
+class Fem:
+    """The tet-FEM domain over (tets, verts); see ebbx_fem_create."""
+
+    def __init__(self, tets: Relation, keyfield: str, verts: Relation, pos_field: str,
+                 pinned_field: Optional[str], model: int, elem_prec: int, E: float, nu: float,
+                 rho: float = 1000.0, E_field: Optional[str] = None, strategy: int = STRAT_ATOMIC,
+                 block: int = 0):
+        p = FemParams(model, elem_prec, rho, E, nu, E_field.encode() if E_field else None, strategy, block)
+        h = C.c_void_p()
+        _check(lib().ebbx_fem_create(tets.h, keyfield.encode(), verts.h, pos_field.encode(),
+                                     pinned_field.encode() if pinned_field else None, C.byref(p),
+                                     C.byref(h)))
+        self.h = h
+        self.tets, self.verts = tets, verts
+        self.nt, self.nv = tets.size, verts.size
+        self.model, self.elem_prec = model, elem_prec
+
+    def close(self):
+        if self.h:
+            _check(lib().ebbx_fem_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_strategy(self, strategy: int, block: int = 0):
+        _check(lib().ebbx_fem_set_strategy(self.h, int(strategy), int(block)))
+
+    def get_strategy(self):
+        s, b = C.c_int32(), C.c_int32()
+        _check(lib().ebbx_fem_get_strategy(self.h, C.byref(s), C.byref(b)))
+        return s.value, b.value
+
+    def _vec(self, t, what):
+        _dev(t, torch.float64, what)
+        if tuple(t.shape) != (3, self.nv):
+            raise ValueError(f"{what}: expected shape (3, {self.nv}), got {tuple(t.shape)}")
+        return t
+
+    def forces(self, d, f=None, accumulate=False, stream=None):
+        self._vec(d, "d")
+        if f is None:
+            f = torch.empty_like(d)
+        self._vec(f, "f")
+        _check(lib().ebbx_fem_forces(self.h, _ptr(d), _ptr(f), int(bool(accumulate)), _stream(stream)))
+        return f
+
+    def kmul(self, d, u, y=None, accumulate=False, stream=None):
+        self._vec(d, "d")
+        self._vec(u, "u")
+        if y is None:
+            y = torch.empty_like(d)
+        self._vec(y, "y")
+        _check(lib().ebbx_fem_Kmul(self.h, _ptr(d), _ptr(u), _ptr(y), int(bool(accumulate)),
+                                   _stream(stream)))
+        return y
+
+    def energy(self, d, stream=None):
+        self._vec(d, "d")
+        out = torch.empty(1, dtype=torch.float64, device=d.device)
+        _check(lib().ebbx_fem_energy(self.h, _ptr(d), _ptr(out), _stream(stream)))
+        return out
+
+    def jacobi_diag(self, d, dt, stream=None):
+        self._vec(d, "d")
+        out = torch.empty_like(d)
+        _check(lib().ebbx_fem_jacobi_diag(self.h, _ptr(d), float(dt), _ptr(out), _stream(stream)))
+        return out
+
+    def mass(self, stream=None):
+        out = torch.empty(self.nv, dtype=torch.float64, device="cuda")
+        _check(lib().ebbx_fem_mass(self.h, _ptr(out), _stream(stream)))
+        return out
+
+    def n_inverted(self, reset=False, stream=None):
+        n = C.c_int64()
+        _check(lib().ebbx_fem_status(self.h, C.byref(n), int(bool(reset)), _stream(stream)))
+        return n.value
+
+    def implicit_step(self, d, v, dt, g=(0.0, 0.0, -9.81), tol=0.0, maxit=100,
+                      precond=PRECOND_JACOBI, stats=None, stream=None):
+        """Advance (d, v) in place; returns the device stats tensor (24 bytes)."""
+        self._vec(d, "d")
+        self._vec(v, "v")
+        if stats is None:
+            stats = torch.zeros(3, dtype=torch.int64, device=d.device)
+        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond))
+        _check(lib().ebbx_implicit_step(self.h, _ptr(d), _ptr(v), C.byref(p), _ptr(stats),
+                                        _stream(stream)))
+        return stats
+
+
+def stats_fetch(stats_dev: torch.Tensor, stream=None) -> StepStats:
+    h = StepStats()
+    _check(lib().ebbx_stats_fetch(_ptr(stats_dev), C.byref(h), _stream(stream)))
+    return h
+
+
+def cache_flush(nbytes: int = 1 << 30, stream=None):
+    _check(lib().ebbx_cache_flush(C.c_size_t(int(nbytes)), _stream(stream)))
+
+
+class FemMesh:
+    """Convenience: relations + bound fields of one tet mesh, then its Fem.
+
+    X: (nv, 3) float64; tets: (nt, 4) int32; pinned: (nv,) uint8 (numpy or
+    torch).  Uploads to the GPU in column-store layout.
+    """
+
+    def __init__(self, X, tets, pinned=None, model=NH, elem_prec=F64, E=1e5, nu=0.3, rho=1000.0,
+                 E_tet=None, strategy=STRAT_ATOMIC, block=0, morton=False):
+        Xd = torch.as_tensor(X, dtype=torch.float64).t().contiguous().cuda()
+        Td = torch.as_tensor(tets).to(torch.int32).t().contiguous().cuda()
+        nv, nt = Xd.shape[1], Td.shape[1]
+        self.verts = Relation("verts", nv)
+        self.tets = Relation("tets", nt)
+        self.verts.bind_field("X", Xd)
+        self.tets.bind_keyfield("v", self.verts, Td)
+        if pinned is not None:
+            self.verts.bind_field("pinned", torch.as_tensor(pinned).to(torch.uint8).contiguous().cuda())
+        if E_tet is not None:
+            self.tets.bind_field("E", torch.as_tensor(E_tet, dtype=torch.float64).contiguous().cuda())
+        self.vperm = self.tperm = None
+        if morton:
+            _codes, self.vperm, self.tperm = morton_order(self.verts, "X", self.tets, "v")
+            self.verts.reorder(self.vperm)
+            self.tets.reorder(self.tperm)
+        self.X, self.T = Xd, Td
+        self.fem = Fem(self.tets, "v", self.verts, "X", "pinned" if pinned is not None else None, model,
+                       elem_prec, E, nu, rho, "E" if E_tet is not None else None, strategy, block)
+
+    @property
+    def nv(self):
+        return self.verts.size
+
+    @property
+    def nt(self):
+        return self.tets.size
+
+    def to_dev(self, a):
+        """(nv, 3) array in the caller's vertex order -> (3, nv) device tensor in library order."""
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if self.vperm is not None:
+            t = t[self.vperm.cpu().long()]
+        return t.t().contiguous().cuda()
+
+    def from_dev(self, t):
+        """(3, nv) device tensor in library order -> (nv, 3) numpy in the caller's vertex order."""
+        a = t.t().cpu().numpy()
+        if self.vperm is not None:
+            out = a.copy()
+            out[self.vperm.cpu().numpy()] = a
+            a = out
+        return a

@@ -1,0 +1,364 @@
+"""GPU path (through the C-ABI) against the CPU oracle on identical seeded inputs.
+
+Tolerances (normwise, ||a - b||_inf / ||b||_inf over the whole vector):
+  FP64 element arithmetic: 1e-10; FP32 element arithmetic (FP64 reduction): 1e-5.
+Integer results (grouping, Morton order) must match bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1506_07577_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1506_07577_amd import ebbx
+else:  # collected on a CPU host only to be deselected
+    ebbx = None
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+STRATS = ["atomic", "seg", "block"]
+
+
+def _strat(name):
+    return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK}[name]
+
+
+def _prec(p):
+    return ebbx.F64 if p == "f64" else ebbx.F32
+
+
+def nerr(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _mesh_small():
+    return mg.jitter(mg.kuhn_cube(8), 0.01, seed=0)
+
+
+# ---------------------------------------------------------------------------
+# relational runtime
+# ---------------------------------------------------------------------------
+
+def test_keyfield_range_validation():
+    v = ebbx.Relation("verts", 10)
+    t = ebbx.Relation("tets", 3)
+    keys = torch.tensor([[0, 1, 2], [3, 4, 5], [6, 7, 8], [9, 9, 10]], dtype=torch.int32, device="cuda")
+    with pytest.raises(ebbx.EbbxError) as e:
+        t.bind_keyfield("v", v, keys)
+    assert e.value.code == ebbx.E_KEY_RANGE
+    keys[3, 2] = -1
+    with pytest.raises(ebbx.EbbxError):
+        t.bind_keyfield("v", v, keys)
+    keys[3, 2] = 9
+    t.bind_keyfield("v", v, keys)
+
+
+@pytest.mark.parametrize("n,scr", [(1, False), (5, True), (8, False), (13, True)])
+def test_group_by_bit_exact(n, scr):
+    m = mg.kuhn_cube(n)
+    if scr:
+        m, _, _ = mg.scramble(m, seed=1)
+    rp_ref, inc_ref = oracle.group_by(m.nv, m.tets)
+    v = ebbx.Relation("verts", m.nv)
+    t = ebbx.Relation("tets", m.nt)
+    t.bind_keyfield("v", v, torch.as_tensor(m.tets.T.copy()).cuda())
+    t.group_by("v")
+    rp, inc = t.group_export("v", m.nv, 4)
+    assert np.array_equal(rp.cpu().numpy(), rp_ref)
+    assert np.array_equal(inc.cpu().numpy(), inc_ref)
+
+
+def test_group_by_ragged_and_isolated():
+    # vertices 0 and 7 have no incident tets; degrees are ragged
+    tets = np.array([[1, 2, 3, 4], [2, 3, 4, 5], [6, 5, 4, 3], [1, 6, 2, 5], [6, 1, 3, 2]], dtype=np.int32)
+    nv = 8
+    rp_ref, inc_ref = oracle.group_by(nv, tets)
+    v = ebbx.Relation("verts", nv)
+    t = ebbx.Relation("tets", len(tets))
+    t.bind_keyfield("v", v, torch.as_tensor(tets.T.copy()).cuda())
+    t.group_by("v")
+    rp, inc = t.group_export("v", nv, 4)
+    assert np.array_equal(rp.cpu().numpy(), rp_ref)
+    assert np.array_equal(inc.cpu().numpy(), inc_ref)
+
+
+@pytest.mark.parametrize("n,flat", [(6, False), (11, True)])
+def test_morton_bit_exact(n, flat):
+    m, _, _ = mg.scramble(mg.jitter(mg.kuhn_cube(n), 0.01, seed=0), seed=1)
+    X = m.X.copy()
+    if flat:
+        X[:, 1] = 0.5
+    codes_ref, vp_ref, tp_ref = oracle.morton(X, m.tets)
+    v = ebbx.Relation("verts", m.nv)
+    t = ebbx.Relation("tets", m.nt)
+    v.bind_field("X", torch.as_tensor(X.T.copy()).cuda())
+    t.bind_keyfield("v", v, torch.as_tensor(m.tets.T.copy()).cuda())
+    codes, vp, tp = ebbx.morton_order(v, "X", t, "v")
+    assert np.array_equal(codes.cpu().numpy().view(np.uint64), codes_ref)
+    assert np.array_equal(vp.cpu().numpy(), vp_ref)
+    assert np.array_equal(tp.cpu().numpy(), tp_ref)
+
+
+def test_reorder_permutes_fields_and_keys():
+    m, _, _ = mg.scramble(mg.kuhn_cube(4), seed=1)
+    v = ebbx.Relation("verts", m.nv)
+    t = ebbx.Relation("tets", m.nt)
+    X = torch.as_tensor(m.X.T.copy()).cuda()
+    K = torch.as_tensor(m.tets.T.copy()).cuda()
+    v.bind_field("X", X)
+    t.bind_keyfield("v", v, K)
+    _c, vp, tp = ebbx.morton_order(v, "X", t, "v")
+    v.reorder(vp)
+    t.reorder(tp)
+    vpn, tpn = vp.cpu().numpy(), tp.cpu().numpy()
+    inv = np.empty(m.nv, dtype=np.int64)
+    inv[vpn] = np.arange(m.nv)
+    assert np.array_equal(X.cpu().numpy().T, m.X[vpn])
+    assert np.array_equal(K.cpu().numpy().T, inv[m.tets[tpn]])
+    bad = torch.zeros(m.nv, dtype=torch.int32, device="cuda")
+    with pytest.raises(ebbx.EbbxError):
+        v.reorder(bad)
+
+
+# ---------------------------------------------------------------------------
+# element map: forces, stiffness product, diagonal, energy
+# ---------------------------------------------------------------------------
+
+def _pair(m, model, prec, strat, E=1e5, nu=0.3, E_tet=None, morton=False):
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=model, elem_prec=_prec(prec), E=E, nu=nu,
+                        E_tet=E_tet, strategy=_strat(strat), morton=morton)
+    ref = oracle.FEM.create(model, m.X, m.tets, E if E_tet is None else E_tet, nu, pinned=m.pinned)
+    return mesh, ref
+
+
+@pytest.mark.parametrize("strat", STRATS)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("model", [0, 1])
+def test_forces_kmul_parity(model, prec, strat):
+    m = _mesh_small()
+    mesh, ref = _pair(m, model, prec, strat)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    u = mg.direction(m, 11)
+    dd, ud = mesh.to_dev(d), mesh.to_dev(u)
+    f = mesh.from_dev(mesh.fem.forces(dd))
+    y = mesh.from_dev(mesh.fem.kmul(dd, ud))
+    assert nerr(f, ref.forces(d)) <= TOL[prec]
+    assert nerr(y, ref.kmul(d, u)) <= TOL[prec]
+    # exactly zero at rest (G-form)
+    z = mesh.to_dev(np.zeros_like(d))
+    assert torch.count_nonzero(mesh.fem.forces(z)).item() == 0
+    # accumulate adds
+    f2 = mesh.fem.forces(dd, f=mesh.fem.forces(dd).clone(), accumulate=True)
+    assert nerr(mesh.from_dev(f2), 2 * ref.forces(d)) <= TOL[prec]
+    mesh.fem.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("model", [0, 1])
+def test_diag_energy_mass_parity(model, prec):
+    m = _mesh_small()
+    mesh, ref = _pair(m, model, prec, "atomic")
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    dd = mesh.to_dev(d)
+    diag = mesh.from_dev(mesh.fem.jacobi_diag(dd, 1e-3))
+    assert nerr(diag, ref.jacobi_diag(d, 1e-3)) <= TOL[prec]
+    W = mesh.fem.energy(dd).item()
+    assert abs(W - ref.energy(d)) <= (1e-10 if prec == "f64" else 1e-6) * abs(ref.energy(d))
+    mass = mesh.fem.mass().cpu().numpy()
+    assert nerr(mass, ref.mass) <= 1e-14
+    mesh.fem.close()
+
+
+def test_per_tet_material():
+    m = _mesh_small()
+    E = 1e5 * np.exp(0.5 * np.random.default_rng(2).standard_normal(m.nt))
+    mesh, ref = _pair(m, 1, "f64", "seg", E_tet=E)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    u = mg.direction(m, 11)
+    assert nerr(mesh.from_dev(mesh.fem.forces(mesh.to_dev(d))), ref.forces(d)) <= 1e-10
+    assert nerr(mesh.from_dev(mesh.fem.kmul(mesh.to_dev(d), mesh.to_dev(u))), ref.kmul(d, u)) <= 1e-10
+    mesh.fem.close()
+
+
+def test_morton_reordered_mesh_same_physics():
+    m, _, _ = mg.scramble(mg.jitter(mg.kuhn_cube(9), 0.01, seed=0), seed=1)
+    mesh, ref = _pair(m, 0, "f64", "block", morton=True)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    u = mg.direction(m, 11)
+    assert nerr(mesh.from_dev(mesh.fem.forces(mesh.to_dev(d))), ref.forces(d)) <= 1e-10
+    assert nerr(mesh.from_dev(mesh.fem.kmul(mesh.to_dev(d), mesh.to_dev(u))), ref.kmul(d, u)) <= 1e-10
+    mesh.fem.close()
+
+
+def test_seg_strategy_bitwise_reproducible():
+    m = _mesh_small()
+    mesh, _ = _pair(m, 1, "f32", "seg")
+    d = mesh.to_dev(mg.perturbed_state(m, 0.02, seed=10))
+    u = mesh.to_dev(mg.direction(m, 11))
+    a = mesh.fem.kmul(d, u).clone()
+    b = mesh.fem.kmul(d, u).clone()
+    assert torch.equal(a, b)
+    mesh.fem.close()
+
+
+def test_phase_rule_and_degenerate():
+    m = _mesh_small()
+    mesh, _ = _pair(m, 0, "f64", "atomic")
+    d = mesh.to_dev(mg.perturbed_state(m, 0.02, seed=10))
+    with pytest.raises(ebbx.EbbxError) as e:
+        mesh.fem.forces(d, f=d)
+    assert e.value.code == ebbx.E_PHASE
+    with pytest.raises(ebbx.EbbxError) as e:
+        mesh.fem.kmul(d, d.clone(), y=d)
+    assert e.value.code == ebbx.E_PHASE
+    mesh.fem.close()
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [1, 1, 0]], dtype=float)
+    with pytest.raises(ebbx.EbbxError) as e:
+        ebbx.FemMesh(X, np.array([[0, 1, 2, 3]]), None, model=0)
+    assert e.value.code == ebbx.E_DEGENERATE
+
+
+def test_single_tet_and_tiny_meshes():
+    for m in [mg.single_tet(), mg.kuhn_cube(1)]:
+        for strat in STRATS:
+            mesh, ref = _pair(m, 1, "f64", strat)
+            d = 0.01 * mg.direction(m, 3)
+            assert nerr(mesh.from_dev(mesh.fem.forces(mesh.to_dev(d))), ref.forces(d)) <= 1e-10
+            mesh.fem.close()
+
+
+# ---------------------------------------------------------------------------
+# implicit step
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_step_small_config(strat):
+    """8^3 cube, jittered, StVK FP64, E=1e5, nu=0.3, dt=1e-3, 50 CG iterations."""
+    w = mg.workload_small()
+    m = w.mesh
+    mesh, ref = _pair(m, w.model, w.prec, strat, E=w.E, nu=w.nu)
+    z = np.zeros((m.nv, 3))
+    d, v = mesh.to_dev(z), mesh.to_dev(z)
+    st = mesh.fem.implicit_step(d, v, w.dt, tol=0.0, maxit=w.maxit)
+    s = ebbx.stats_fetch(st)
+    d1, v1, _dv, so = ref.implicit_step(z, z, w.dt, tol=0.0, maxit=w.maxit)
+    assert s.status == 0 and s.iters == w.maxit == so.iters
+    assert nerr(mesh.from_dev(v), v1) <= 1e-10
+    assert nerr(mesh.from_dev(d), d1) <= 1e-10
+    # a second step from the new state
+    st = mesh.fem.implicit_step(d, v, w.dt, tol=0.0, maxit=w.maxit)
+    d2, v2, _dv, _ = ref.implicit_step(d1, v1, w.dt, tol=0.0, maxit=w.maxit)
+    assert nerr(mesh.from_dev(v), v2) <= 1e-10
+    mesh.fem.close()
+
+
+@pytest.mark.parametrize("precond", [0, 1])
+def test_step_tolerance_and_iterations(precond):
+    m = mg.jitter(mg.kuhn_cube(6), 0.01, seed=0)
+    mesh, ref = _pair(m, 1, "f64", "seg", E=1e6, nu=0.45)
+    d0 = mg.perturbed_state(m, 0.02, seed=10)
+    v0 = 0.1 * mg.direction(m, 11)
+    d, v = mesh.to_dev(d0), mesh.to_dev(v0)
+    st = mesh.fem.implicit_step(d, v, 1e-3, tol=1e-8, maxit=1000, precond=precond)
+    s = ebbx.stats_fetch(st)
+    _d1, v1, _dv, so = ref.implicit_step(d0, v0, 1e-3, tol=1e-8, maxit=1000, precond=precond)
+    assert s.status == 0 and abs(s.iters - so.iters) <= 2
+    assert s.rel_res <= 1e-8
+    assert nerr(mesh.from_dev(v), v1) <= 1e-7
+    mesh.fem.close()
+
+
+def test_step_error_conditions():
+    m = mg.kuhn_cube(3)
+    # maxit reached with a tolerance: NOT_CONVERGED, iterate kept
+    mesh, ref = _pair(m, 0, "f64", "atomic", E=1e7)
+    z = np.zeros((m.nv, 3))
+    d, v = mesh.to_dev(z), mesh.to_dev(z)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-2, tol=1e-30, maxit=2))
+    assert s.status == ebbx.E_NOT_CONVERGED and s.iters == 2
+    _d, v1, _dv, _ = ref.implicit_step(z, z, 1e-2, tol=1e-30, maxit=2)
+    assert nerr(mesh.from_dev(v), v1) <= 1e-10
+    mesh.fem.close()
+    # negative stiffness: p^T A p <= 0 -> NOT_SPD, state unchanged
+    mesh, _ = _pair(m, 0, "f64", "atomic", E=-1e9)
+    d, v = mesh.to_dev(z), mesh.to_dev(z)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-2, tol=0.0, maxit=50, precond=0))
+    assert s.status == ebbx.E_NOT_SPD
+    assert torch.count_nonzero(v).item() == 0
+    mesh.fem.close()
+    # inverted neo-Hookean element: reported, state unchanged
+    mesh, _ = _pair(m, 1, "f64", "atomic")
+    dinv = np.zeros((m.nv, 3))
+    dinv[:, 0] = -2.0 * m.X[:, 0]
+    d, v = mesh.to_dev(dinv), mesh.to_dev(z)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-3, maxit=5))
+    assert s.status == ebbx.E_INVERTED and s.n_inverted > 0
+    assert torch.count_nonzero(v).item() == 0
+    mesh.fem.close()
+
+
+def test_free_fall_unpinned():
+    m = mg.jitter(mg.kuhn_cube(4), 0.01, seed=0)
+    mesh = ebbx.FemMesh(m.X, m.tets, None, model=1, elem_prec=ebbx.F64, E=1e5, nu=0.3)
+    z = np.zeros((m.nv, 3))
+    d, v = mesh.to_dev(z), mesh.to_dev(z)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-3, tol=1e-15, maxit=500))
+    vv = mesh.from_dev(v)
+    assert np.abs(vv - np.array([0, 0, -9.81e-3])).max() <= 1e-12 * 9.81e-3
+    mesh.fem.close()
+
+
+# ---------------------------------------------------------------------------
+# full-size workloads
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_plain_workload_full_size(strat):
+    """64^3 cube (1,572,864 tets), neo-Hookean, FP32 element math: forces and
+    K u over the whole mesh against the oracle, 1e-5 normwise."""
+    w = mg.workload_plain()
+    m = w.mesh
+    mesh, ref = _pair(m, w.model, w.prec, strat, E=w.E, nu=w.nu)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    u = mg.direction(m, 11)
+    dd, ud = mesh.to_dev(d), mesh.to_dev(u)
+    assert nerr(mesh.from_dev(mesh.fem.forces(dd)), ref.forces(d)) <= 1e-5
+    assert nerr(mesh.from_dev(mesh.fem.kmul(dd, ud)), ref.kmul(d, u)) <= 1e-5
+    mesh.fem.close()
+
+
+def test_plain_workload_step_residual():
+    """One implicit step of the 64^3 NH FP32 workload (100 CG iterations): the
+    oracle recomputes the FP64 residual ||Pi(b - A dv)|| / ||Pi b|| of the GPU
+    iterate, which must match the GPU's own report up to FP32 element error."""
+    w = mg.workload_plain()
+    m = w.mesh
+    mesh, ref = _pair(m, w.model, w.prec, "atomic", E=w.E, nu=w.nu)
+    d0 = mg.perturbed_state(m, 0.02, seed=10)
+    z = np.zeros((m.nv, 3))
+    d, v = mesh.to_dev(d0), mesh.to_dev(z)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, w.dt, tol=0.0, maxit=w.maxit))
+    assert s.status == 0 and s.iters == w.maxit
+    dv = mesh.from_dev(v)
+    dt = w.dt
+    g = np.array([0.0, 0.0, -9.81])
+    b = dt * (ref.forces(d0) + ref.mass[:, None] * g)
+    Ad = ref.mass[:, None] * dv - dt * dt * ref.kmul(d0, dv)
+    free = (m.pinned == 0)[:, None]
+    r = np.linalg.norm(((b - Ad) * free).ravel()) / np.linalg.norm((b * free).ravel())
+    assert r <= max(10 * s.rel_res, 1e-5)
+    assert np.all(dv[m.pinned == 1] == 0)
+    mesh.fem.close()
