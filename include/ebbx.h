@@ -146,14 +146,24 @@ ebbx_status ebbx_relation_reorder(ebbx_relation rel, const int32_t *new_to_old_d
 
 enum { EBBX_STVK = 0, EBBX_NH = 1 };
 /* Scatter-reduce of per-tet results into vertex fields:
- *   ATOMIC: FP64 hardware atomics, one per (tet, corner, component);
- *   SEG:    per-corner partials, then a vertex-owned sum over the grouping's
- *           incidence in fixed order (bitwise deterministic);
- *   BLOCK:  tets processed in blocks that stage their vertices in LDS and
- *           pre-reduce there; vertices whose incident tets all lie in the
- *           block are stored, the rest added atomically;
- *   AUTO:   the library's choice (the autotuner's, if it ran). */
-enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3 };
+ *   ATOMIC:    FP64 hardware atomics, one per (tet, corner, component);
+ *   SEG:       per-corner partials, then a vertex-owned sum over the grouping's
+ *              incidence in fixed order (bitwise deterministic);
+ *   BLOCK:     consecutive tets form blocks (best after Morton reordering);
+ *              a block stages its vertices' fields in LDS, sums each vertex's
+ *              contributions over a precomputed incidence list in fixed order,
+ *              stores the vertices whose incident tets all lie in the block,
+ *              and writes partial sums of the others to a halo buffer that a
+ *              vertex pass sums in block order: no global atomics, bitwise
+ *              deterministic;
+ *   BLOCK_LDS: as BLOCK, but the in-block sums use FP64 LDS atomics (not
+ *              bitwise reproducible);
+ *   AUTO:      the library's choice.
+ * The `block` argument of the calls below is the workgroup size (threads) for
+ * ATOMIC and SEG, and the number of tets per block (64..512, a power of two)
+ * for BLOCK and BLOCK_LDS; 0 picks the default. */
+enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3,
+       EBBX_STRAT_BLOCK_LDS = 4 };
 
 typedef struct {
     int32_t model;       /* EBBX_STVK or EBBX_NH */
@@ -163,7 +173,7 @@ typedef struct {
     double nu;           /* Poisson's ratio, in (-1, 0.5) */
     const char *E_field; /* nullable: FP64 (1, nt) per-tet Young's modulus on tets */
     int32_t strategy;    /* EBBX_STRAT_* */
-    int32_t block;       /* threads per block for the element kernels, 0 = default */
+    int32_t block;       /* see the strategies above; 0 = default */
 } ebbx_fem_params;
 
 /* Build the FEM domain over `tets` (key-field `keyfield`, arity 4, target

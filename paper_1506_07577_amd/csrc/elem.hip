@@ -1,14 +1,24 @@
 // elem.hip -- the element-parallel map over the tets relation.
 //
-// One thread per tet (the paper's GPU specialisation maps one relation row to
-// one thread; Runtime Implementation, "CPU/GPU Specialization").  Each thread
-// gathers the vertex fields of its four corners through the tets.v key-field,
-// evaluates the hyperelastic element quantity and reduces (+=) twelve results
-// into a vertex field (Runtime Implementation, "Reductions").  The per-tet
-// quantities are those of the paper's Vega (StVK) and FreeFem++ (neo-Hookean)
-// workloads (Performance Evaluation); the textbook formulas are written in the
-// displacement-gradient form G = dD B, F = I + G, so that single precision
-// keeps its accuracy near the rest shape (no F - I or F - F^-T cancellation).
+// Each tet gathers the vertex fields of its four corners through the tets.v
+// key-field, evaluates its hyperelastic element quantity and reduces (+=)
+// twelve results into a vertex field (Runtime Implementation, "CPU/GPU
+// Specialization" and "Reductions").  The per-tet quantities are those of the
+// paper's Vega (StVK) and FreeFem++ (neo-Hookean) workloads (Performance
+// Evaluation), written in the displacement-gradient form G = dD B, F = I + G,
+// so that single precision keeps its accuracy near the rest shape (no F - I
+// or F - F^-T cancellation).
+//
+// Three reductions:
+//  - ATOMIC: one thread per tet, FP64 device-scope atomics (the paper's GPU
+//    field reduction);
+//  - SEG:    one thread per tet writes its per-corner partials, then one thread
+//    per vertex sums them over the grouping's incidence in a fixed order;
+//  - BLOCK:  a workgroup takes a block of consecutive (Morton-ordered) tets,
+//    stages the block's vertices in LDS, evaluates, reduces into LDS, stores
+//    the vertices it owns outright and writes partials of vertices shared with
+//    other blocks to a halo buffer that a vertex pass sums in a fixed order.
+//    No global atomics.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -18,11 +28,40 @@
 
 namespace ebbx {
 
-enum Scatter { SC_ATOMIC = 0, SC_PART = 1, SC_BLOCK = 2 };
+enum Scatter { SC_ATOMIC = 0, SC_PART = 1 };
 
-template <class T> __device__ __forceinline__ T t_log1p(T x);
-template <> __device__ __forceinline__ float t_log1p<float>(float x) { return log1pf(x); }
-template <> __device__ __forceinline__ double t_log1p<double>(double x) { return log1p(x); }
+// ---- scalar helpers ------------------------------------------------------------
+
+// Element idx of a column: a 64-bit base in scalar registers plus a 32-bit byte
+// offset (sizes are checked on the host so that idx * sizeof(T) fits 32 bits).
+template <class T> __device__ __forceinline__ T ldc(const void *base, uint32_t idx) {
+    return *(const T *)((const char *)base + idx * (uint32_t)sizeof(T));
+}
+template <class T> __device__ __forceinline__ void stc(void *base, uint32_t idx, T v) {
+    *(T *)((char *)base + idx * (uint32_t)sizeof(T)) = v;
+}
+template <class T> __device__ __forceinline__ T *atc(void *base, uint32_t idx) {
+    return (T *)((char *)base + idx * (uint32_t)sizeof(T));
+}
+
+__device__ __forceinline__ float t_rcp(float x) { return __builtin_amdgcn_rcpf(x); }   // 1 ulp
+__device__ __forceinline__ double t_rcp(double x) { return 1.0 / x; }
+
+// ln(1 + x).  Near zero (|x| < 1/4, the range of elastic volume change met in
+// practice) through ln(1+x) = 2 atanh(s), s = x / (2 + x), and the odd series
+// of atanh to s^9 (truncation below 1e-9 relative); elsewhere the library log1p.
+__device__ __forceinline__ float t_log1p(float x) {
+    if (fabsf(x) < 0.25f) {
+        const float s = x * __builtin_amdgcn_rcpf(2.0f + x);
+        const float s2 = s * s;
+        float p = fmaf(s2, 1.0f / 9.0f, 1.0f / 7.0f);
+        p = fmaf(s2, p, 0.2f);
+        p = fmaf(s2, p, 1.0f / 3.0f);
+        return 2.0f * fmaf(s * s2, p, s);
+    }
+    return log1pf(x);
+}
+__device__ __forceinline__ double t_log1p(double x) { return log1p(x); }
 
 // ---- 3x3 algebra on registers (row-major, M[3*i + j]) ---------------------------
 
@@ -37,6 +76,15 @@ template <class T> __device__ __forceinline__ void mul3(const T *A, const T *B, 
     for (int i = 0; i < 3; ++i)
 #pragma unroll
         for (int j = 0; j < 3; ++j) C[3 * i + j] = A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
+}
+
+// C = A0 + A B
+template <class T> __device__ __forceinline__ void muladd3(const T *A0, const T *A, const T *B, T *C) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            C[3 * i + j] = A0[3 * i + j] + A[3 * i] * B[j] + A[3 * i + 1] * B[3 + j] + A[3 * i + 2] * B[6 + j];
 }
 
 // C = A^T B
@@ -78,108 +126,109 @@ template <class T> __device__ __forceinline__ T jm1_of(const T *G) {
     return tr + T(0.5) * (tr * tr - trGG) + det3(G);
 }
 
-// ---- constitutive models -----------------------------------------------------------
-
-// StVK: S = 2 mu E + lam tr(E) I with E = (G + G^T + G^T G)/2 (symmetric, full 3x3)
-template <class T> __device__ __forceinline__ void stvk_S(T mu, T lam, const T *G, T *S) {
-    T GtG[9];
-    mulTN3(G, G, GtG);
-    T E[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) E[3 * i + j] = T(0.5) * (G[3 * i + j] + G[3 * j + i] + GtG[3 * i + j]);
-    const T le = lam * (E[0] + E[4] + E[8]);
-#pragma unroll
-    for (int k = 0; k < 9; ++k) S[k] = T(2) * mu * E[k];
-    S[0] += le;
-    S[4] += le;
-    S[8] += le;
+// G^T G (symmetric), as the full 3x3
+template <class T> __device__ __forceinline__ void gtg_sym(const T *G, T *S) {
+    S[0] = G[0] * G[0] + G[3] * G[3] + G[6] * G[6];
+    S[4] = G[1] * G[1] + G[4] * G[4] + G[7] * G[7];
+    S[8] = G[2] * G[2] + G[5] * G[5] + G[8] * G[8];
+    S[1] = S[3] = G[0] * G[1] + G[3] * G[4] + G[6] * G[7];
+    S[2] = S[6] = G[0] * G[2] + G[3] * G[5] + G[6] * G[8];
+    S[5] = S[7] = G[1] * G[2] + G[4] * G[5] + G[7] * G[8];
 }
 
-// P(F) in G-form.  Returns false for an inverted neo-Hookean element.
-template <class T, int MODEL> __device__ __forceinline__ bool stress(T mu, T lam, const T *G, T *P) {
+// ---- constitutive models: each returns -V0 P (or -V0 dP) -----------------------------
+
+// StVK S = 2 mu E + lam tr(E) I, E = (G + G^T + G^T G)/2, scaled by `sc`
+template <class T> __device__ __forceinline__ void stvk_S(T mu, T lam, const T *G, T sc, T *S) {
+    T Q[9];
+    gtg_sym(G, Q);
+    const T e00 = G[0] + T(0.5) * Q[0], e11 = G[4] + T(0.5) * Q[4], e22 = G[8] + T(0.5) * Q[8];
+    const T e01 = T(0.5) * (G[1] + G[3] + Q[1]), e02 = T(0.5) * (G[2] + G[6] + Q[2]),
+            e12 = T(0.5) * (G[5] + G[7] + Q[5]);
+    const T m2 = T(2) * mu * sc, le = lam * (e00 + e11 + e22) * sc;
+    S[0] = m2 * e00 + le;
+    S[4] = m2 * e11 + le;
+    S[8] = m2 * e22 + le;
+    S[1] = S[3] = m2 * e01;
+    S[2] = S[6] = m2 * e02;
+    S[5] = S[7] = m2 * e12;
+}
+
+// -V0 P(F); returns false for an inverted neo-Hookean element
+template <class T, int MODEL> __device__ __forceinline__ bool stress_scaled(T mu, T lam, T V0, const T *G, T *P) {
     if (MODEL == EBBX_STVK) {
-        T S[9], GS[9];
-        stvk_S(mu, lam, G, S);
-        mul3(G, S, GS);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) P[k] = S[k] + GS[k];   // P = (I + G) S
+        T S[9];
+        stvk_S(mu, lam, G, -V0, S);
+        muladd3(S, G, S, P);   // P = S + G S
         return true;
     } else {
         // P = F^-T [mu (G + G^T + G^T G) + lam ln J I] = cof(F) M / J
         const T jm1 = jm1_of(G);
         const T J = T(1) + jm1;
+        const T iJ = t_rcp(J);
         const T lnJ = t_log1p(jm1);
-        T GtG[9], M[9], C[9];
-        mulTN3(G, G, GtG);
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) M[3 * i + j] = mu * (G[3 * i + j] + G[3 * j + i] + GtG[3 * i + j]);
-        const T ll = lam * lnJ;
-        M[0] += ll;
-        M[4] += ll;
-        M[8] += ll;
+        T Q[9], M[9], C[9];
+        gtg_sym(G, Q);
+        const T ms = -V0 * iJ * mu, ll = -V0 * iJ * lam * lnJ;
+        M[0] = ms * (T(2) * G[0] + Q[0]) + ll;
+        M[4] = ms * (T(2) * G[4] + Q[4]) + ll;
+        M[8] = ms * (T(2) * G[8] + Q[8]) + ll;
+        M[1] = M[3] = ms * (G[1] + G[3] + Q[1]);
+        M[2] = M[6] = ms * (G[2] + G[6] + Q[2]);
+        M[5] = M[7] = ms * (G[5] + G[7] + Q[5]);
         cof_IpG(G, C);
         mul3(C, M, P);
-        const T iJ = T(1) / J;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) P[k] *= iJ;
         return J > T(0);
     }
 }
 
-// dP = dP/dF : dF at G.
-template <class T, int MODEL> __device__ __forceinline__ bool dstress(T mu, T lam, const T *G, const T *dF, T *dP) {
+// -V0 dP, dP = dP/dF : dF at G
+template <class T, int MODEL>
+__device__ __forceinline__ bool dstress_scaled(T mu, T lam, T V0, const T *G, const T *dF, T *dP) {
     if (MODEL == EBBX_STVK) {
         // dP = dF S + F dS, dS = 2 mu sym(F^T dF) + lam tr(F^T dF) I
-        T S[9], A[9], GtdF[9];
-        stvk_S(mu, lam, G, S);
+        T S[9], A[9];
+        stvk_S(mu, lam, G, -V0, S);
+        T GtdF[9];
         mulTN3(G, dF, GtdF);
 #pragma unroll
         for (int k = 0; k < 9; ++k) A[k] = dF[k] + GtdF[k];   // F^T dF
+        const T mv = -V0 * mu, lt = -V0 * lam * (A[0] + A[4] + A[8]);
         T dS[9];
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) dS[3 * i + j] = mu * (A[3 * i + j] + A[3 * j + i]);
-        const T lt = lam * (A[0] + A[4] + A[8]);
-        dS[0] += lt;
-        dS[4] += lt;
-        dS[8] += lt;
-        T dFS[9], GdS[9];
-        mul3(dF, S, dFS);
-        mul3(G, dS, GdS);
-#pragma unroll
-        for (int k = 0; k < 9; ++k) dP[k] = dFS[k] + dS[k] + GdS[k];
+        dS[0] = T(2) * mv * A[0] + lt;
+        dS[4] = T(2) * mv * A[4] + lt;
+        dS[8] = T(2) * mv * A[8] + lt;
+        dS[1] = dS[3] = mv * (A[1] + A[3]);
+        dS[2] = dS[6] = mv * (A[2] + A[6]);
+        dS[5] = dS[7] = mv * (A[5] + A[7]);
+        T X[9];
+        muladd3(dS, G, dS, X);   // F dS = dS + G dS
+        muladd3(X, dF, S, dP);   // + dF S
         return true;
     } else {
-        // dP = mu dF + (mu - lam ln J) N dF^T N + lam (N : dF) N, N = F^-T
+        // dP = mu dF + (mu - lam ln J) N dF^T N + lam (N : dF) N, N = cof(F) / J
         const T jm1 = jm1_of(G);
         const T J = T(1) + jm1;
+        const T iJ = t_rcp(J);
         const T lnJ = t_log1p(jm1);
-        T N[9];
-        cof_IpG(G, N);
-        const T iJ = T(1) / J;
-#pragma unroll
-        for (int k = 0; k < 9; ++k) N[k] *= iJ;
+        T C[9];
+        cof_IpG(G, C);
         T X[9], Y[9];
-        mulNT3(N, dF, X);   // N dF^T
-        mul3(X, N, Y);      // N dF^T N
-        T ndf = T(0);
+        mulNT3(C, dF, X);   // C dF^T
+        mul3(X, C, Y);      // C dF^T C
+        T cdf = T(0);
 #pragma unroll
-        for (int k = 0; k < 9; ++k) ndf += N[k] * dF[k];
-        const T c = mu - lam * lnJ;
-        const T ln = lam * ndf;
+        for (int k = 0; k < 9; ++k) cdf += C[k] * dF[k];
+        const T iJ2 = iJ * iJ;
+        const T a = -V0 * mu, bY = -V0 * (mu - lam * lnJ) * iJ2, bC = -V0 * lam * cdf * iJ2;
 #pragma unroll
-        for (int k = 0; k < 9; ++k) dP[k] = mu * dF[k] + c * Y[k] + ln * N[k];
+        for (int k = 0; k < 9; ++k) dP[k] = a * dF[k] + bY * Y[k] + bC * C[k];
         return J > T(0);
     }
 }
 
-// The 12 diagonal entries K[(a,c),(a,c)] = -V0 dP(e_c b_a^T) : (e_c b_a^T) of one tet,
-// in closed form for a rank-one dF = e_c b^T:
+// The 12 diagonal entries K[(a,c),(a,c)] = -V0 dP(e_c b_a^T) : (e_c b_a^T) of one
+// tet, in closed form for a rank-one dF = e_c b^T:
 //   StVK: b^T S b + mu (|f_c|^2 |b|^2 + (f_c . b)^2) + lam (f_c . b)^2, f_c = row c of F
 //   NH:   mu |b|^2 + (mu + lam (1 - ln J)) ((N b)_c)^2
 template <class T, int MODEL> __device__ __forceinline__ bool diag12(T mu, T lam, const T *G, const T *b, T V0, T *h) {
@@ -193,7 +242,7 @@ template <class T, int MODEL> __device__ __forceinline__ bool diag12(T mu, T lam
     }
     if (MODEL == EBBX_STVK) {
         T S[9];
-        stvk_S(mu, lam, G, S);
+        stvk_S(mu, lam, G, T(1), S);
         T F[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) F[k] = G[k];
@@ -203,9 +252,9 @@ template <class T, int MODEL> __device__ __forceinline__ bool diag12(T mu, T lam
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const T *v = ba[a];
-            T Sb0 = S[0] * v[0] + S[1] * v[1] + S[2] * v[2];
-            T Sb1 = S[3] * v[0] + S[4] * v[1] + S[5] * v[2];
-            T Sb2 = S[6] * v[0] + S[7] * v[1] + S[8] * v[2];
+            const T Sb0 = S[0] * v[0] + S[1] * v[1] + S[2] * v[2];
+            const T Sb1 = S[3] * v[0] + S[4] * v[1] + S[5] * v[2];
+            const T Sb2 = S[6] * v[0] + S[7] * v[1] + S[8] * v[2];
             const T bSb = v[0] * Sb0 + v[1] * Sb1 + v[2] * Sb2;
             const T bb = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
 #pragma unroll
@@ -219,10 +268,10 @@ template <class T, int MODEL> __device__ __forceinline__ bool diag12(T mu, T lam
     } else {
         const T jm1 = jm1_of(G);
         const T J = T(1) + jm1;
+        const T iJ = t_rcp(J);
         const T lnJ = t_log1p(jm1);
         T N[9];
         cof_IpG(G, N);
-        const T iJ = T(1) / J;
 #pragma unroll
         for (int k = 0; k < 9; ++k) N[k] *= iJ;
         const T cc = mu + lam * (T(1) - lnJ);
@@ -243,8 +292,7 @@ template <class T, int MODEL> __device__ __forceinline__ bool diag12(T mu, T lam
 // ---- gather / element evaluation ----------------------------------------------------
 
 // M = dD B with dD = [q1-q0 | q2-q0 | q3-q0]; differences in FP64, then rounded to T
-template <class T>
-__device__ __forceinline__ void grad_from(const double (&q)[4][3], const T *b, T *M) {
+template <class T> __device__ __forceinline__ void grad_from(const double (&q)[4][3], const T *b, T *M) {
     T D[9];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
@@ -253,17 +301,17 @@ __device__ __forceinline__ void grad_from(const double (&q)[4][3], const T *b, T
     mul3(D, b, M);
 }
 
-// H = -V0 P B^T -> corners 1..3 get the columns of H, corner 0 minus their sum
-template <class T> __device__ __forceinline__ void corner_forces(const T *P, const T *b, T V0, T *h) {
+// H = Ps B^T (Ps already carries -V0): corners 1..3 get the columns of H,
+// corner 0 minus their sum.  h[3 a + r].
+template <class T> __device__ __forceinline__ void corner_out(const T *Ps, const T *b, T *h) {
     T H[9];
-    mulNT3(P, b, H);
+    mulNT3(Ps, b, H);
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
-        const T h1 = -V0 * H[3 * r], h2 = -V0 * H[3 * r + 1], h3 = -V0 * H[3 * r + 2];
-        h[3 + r] = h1;
-        h[6 + r] = h2;
-        h[9 + r] = h3;
-        h[r] = -(h1 + h2 + h3);
+        h[3 + r] = H[3 * r];
+        h[6 + r] = H[3 * r + 1];
+        h[9 + r] = H[3 * r + 2];
+        h[r] = -(H[3 * r] + H[3 * r + 1] + H[3 * r + 2]);
     }
 }
 
@@ -274,122 +322,280 @@ __device__ __forceinline__ bool eval_tet(T mu, T lam, const T *b, T V0, const do
     grad_from(qd, b, G);
     if (OP == OP_FORCE) {
         T P[9];
-        bool ok = stress<T, MODEL>(mu, lam, G, P);
-        corner_forces(P, b, V0, h);
+        const bool ok = stress_scaled<T, MODEL>(mu, lam, V0, G, P);
+        corner_out(P, b, h);
         return ok;
     } else if (OP == OP_KMUL) {
         T dF[9], dP[9];
         grad_from(qu, b, dF);
-        bool ok = dstress<T, MODEL>(mu, lam, G, dF, dP);
-        corner_forces(dP, b, V0, h);
+        const bool ok = dstress_scaled<T, MODEL>(mu, lam, V0, G, dF, dP);
+        corner_out(dP, b, h);
         return ok;
     } else {
         return diag12<T, MODEL>(mu, lam, G, b, V0, h);
     }
 }
 
-// ---- the element kernel ------------------------------------------------------------
+// ---- one thread per tet: atomic or segmented reduction ------------------------------
 
 template <class T, int MODEL, int OP, int SC>
 __global__ __launch_bounds__(256) void k_elem(ElemArgs a) {
-    const int64_t nt = a.nt, nv = a.nv;
-    extern __shared__ double s_dyn[];
     if (a.skip && *a.skip) return;   // uniform over the grid
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-
-    // block strategy: stage the block's vertices in LDS
-    int nvb = 0, vbase = 0;
-    double *s_d = s_dyn, *s_u = nullptr, *s_acc = nullptr;
-    if (SC == SC_BLOCK) {
-        vbase = a.blk_vptr[blockIdx.x];
-        nvb = a.blk_vptr[blockIdx.x + 1] - vbase;
-        const int nq = (OP == OP_KMUL) ? 2 : 1;
-        s_u = s_d + 3 * nvb;
-        s_acc = s_d + 3 * nq * nvb;
-        for (int i = threadIdx.x; i < nvb; i += blockDim.x) {
-            const int64_t gv = a.blk_verts[vbase + i];
+    const uint32_t nt = a.nt;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    T b[9];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                s_d[k * nvb + i] = a.d[k * nv + gv];
-                if (OP == OP_KMUL) s_u[k * nvb + i] = a.u[k * nv + gv];
-                s_acc[k * nvb + i] = 0.0;
-            }
-        }
-        __syncthreads();
+    for (int k = 0; k < 9; ++k) b[k] = ldc<T>(a.B[k], t);
+    const T V0 = ldc<T>(a.V0, t);
+    T mu, lam;
+    if (a.mu_t) {
+        mu = ldc<T>(a.mu_t, t);
+        lam = ldc<T>(a.lam_t, t);
+    } else {
+        mu = (T)a.mu;
+        lam = (T)a.lam;
     }
-
-    if (t < nt) {
-        const T *Bp = (const T *)a.B;
-        T b[9];
+    uint32_t v[4];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) b[k] = Bp[k * nt + t];
-        const T V0 = ((const T *)a.V0)[t];
-        T mu, lam;
-        if (a.mat) {
-            mu = ((const T *)a.mat)[t];
-            lam = ((const T *)a.mat)[nt + t];
-        } else {
-            mu = (T)a.mu;
-            lam = (T)a.lam;
+    for (int c = 0; c < 4; ++c) v[c] = (uint32_t)ldc<int32_t>(a.key[c], t);
+    double qd[4][3], qu[4][3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            qd[c][k] = ldc<double>(a.d[k], v[c]);
+            qu[c][k] = (OP == OP_KMUL) ? ldc<double>(a.u[k], v[c]) : 0.0;
         }
-        double qd[4][3], qu[4][3];
-        int slot[4];
-        int64_t v[4];
-        if (SC == SC_BLOCK) {
+    T h[12];
+    const bool ok = eval_tet<T, MODEL, OP>(mu, lam, b, V0, qd, qu, h);
+    if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv, 1ull);
+    if (SC == SC_ATOMIC) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) slot[c] = a.blk_local[c * nt + t];
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) atomicAdd(atc<double>(a.out[k], v[c]), (double)h[3 * c + k]);
+    } else {
+        T *pp = (T *)a.part + 12 * (size_t)t;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) pp[k] = h[k];
+    }
+}
+
+// ---- tet blocks staged in LDS --------------------------------------------------------
+//
+// Block b holds tets [b*BT, (b+1)*BT), BT = blockDim.x * TPT.  Its vertex list
+// blk_verts[vptr[b] .. vptr[b+1]) is sorted; each corner carries its slot in
+// that list (packed: 4 x 8 bits per word when every block has <= 256 vertices,
+// else 2 x 16 bits in each of two words).
+
+template <int W> __device__ __forceinline__ void unpack_slots(const ElemArgs &a, uint32_t t, uint32_t *s) {
+    if (W == 1) {
+        const uint32_t w = ldc<uint32_t>(a.slot[0], t);
+        s[0] = w & 255u;
+        s[1] = (w >> 8) & 255u;
+        s[2] = (w >> 16) & 255u;
+        s[3] = w >> 24;
+    } else {
+        const uint32_t w0 = ldc<uint32_t>(a.slot[0], t), w1 = ldc<uint32_t>(a.slot[1], t);
+        s[0] = w0 & 65535u;
+        s[1] = w0 >> 16;
+        s[2] = w1 & 65535u;
+        s[3] = w1 >> 16;
+    }
+}
+
+// LDS layout: the block's incidence lists (copied with 16-byte loads), the
+// block's vertex fields with one column per component (d, and u for the
+// stiffness product), then the per-tet results, one column per (corner,
+// component) pair, each tet writing its own row.  Each block vertex is then
+// summed by one thread over its incidence list (fixed order, FP64) and either
+// stored (the block owns the vertex) or written to the halo.  Every global
+// load that does not depend on another is issued at kernel start.
+template <class T>
+__device__ __forceinline__ void reduce_slot(const ElemArgs &a, const uint16_t *s_list, const T *s_h, uint32_t BT,
+                                            uint32_t bsh, uint32_t gv, int32_t hp, int32_t j0, int32_t j1) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+    for (int32_t j = j0; j < j1; ++j) {
+        const uint32_t e = s_list[j];   // c * BT + local tet
+        const uint32_t c = e >> bsh, tl = e & (BT - 1);
+        const T *p = s_h + 3 * c * BT + tl;
+        a0 += (double)p[0];
+        a1 += (double)p[BT];
+        a2 += (double)p[2 * BT];
+    }
+    if (hp < 0) {
+        // every incident tet is in this block: sole writer
+        if (a.accumulate) {
+            a0 += ldc<double>(a.out[0], gv);
+            a1 += ldc<double>(a.out[1], gv);
+            a2 += ldc<double>(a.out[2], gv);
+        }
+        stc<double>(a.out[0], gv, a0);
+        stc<double>(a.out[1], gv, a1);
+        stc<double>(a.out[2], gv, a2);
+    } else {
+        stc<double>(a.halo[0], (uint32_t)hp, a0);
+        stc<double>(a.halo[1], (uint32_t)hp, a1);
+        stc<double>(a.halo[2], (uint32_t)hp, a2);
+    }
+}
+
+template <class T, int MODEL, int OP, int TPT, int W, int RED>
+__global__ __launch_bounds__(256) void k_block(ElemArgs a) {
+    extern __shared__ uint4 s_dyn4[];
+    if (a.skip && *a.skip) return;   // uniform over the grid
+    const uint32_t nt = a.nt;
+    const uint32_t tid = threadIdx.x, nthr = blockDim.x, BT = nthr * TPT;
+    const uint32_t bsh = 31u - __clz(BT);   // BT is a power of two
+    const uint32_t vb = (uint32_t)a.blk_vptr[blockIdx.x];
+    const uint32_t nvb = (uint32_t)a.blk_vptr[blockIdx.x + 1] - vb;
+    const uint32_t t0 = blockIdx.x * BT;
+    // RED == 0: incidence lists + per-tet result rows (deterministic sums);
+    // RED == 1: FP64 LDS atomics into one accumulator per block vertex
+    uint16_t *s_list = (uint16_t *)s_dyn4;                       // 4 BT + 8 entries
+    double *s_d = (double *)((char *)s_dyn4 + (RED == 0 ? 8 * BT + 16 : 0));
+    double *s_u = s_d + 3 * nvb;
+    T *s_h = (T *)(s_d + (OP == OP_KMUL ? 6 : 3) * nvb);
+    double *s_acc = (double *)s_h;
+
+    // this thread's first block vertex
+    const bool has = tid < nvb;
+    uint32_t gv0 = 0;
+    int32_t hp0 = -1, j00 = 0, j10 = 0;
+    if (has) {
+        gv0 = (uint32_t)a.blk_verts[vb + tid];
+        hp0 = a.blk_hpos[vb + tid];
+        if (RED == 0) {
+            j00 = a.blk_lptr[vb + tid];
+            j10 = a.blk_lptr[vb + tid + 1];
+        }
+    }
+    // per-tet streams
+    T b[TPT][9], V0[TPT], mu[TPT], lam[TPT];
+    uint32_t sl[TPT][4];
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+        const uint32_t t = t0 + r * nthr + tid;
+        if (t < nt) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) b[r][k] = ldc<T>(a.B[k], t);
+            V0[r] = ldc<T>(a.V0, t);
+            if (a.mu_t) {
+                mu[r] = ldc<T>(a.mu_t, t);
+                lam[r] = ldc<T>(a.lam_t, t);
+            } else {
+                mu[r] = (T)a.mu;
+                lam[r] = (T)a.lam;
+            }
+            unpack_slots<W>(a, t, sl[r]);
+        }
+    }
+    int32_t l0 = 0;
+    if (RED == 0) {
+        // the block's incidence lists, copied with 16-byte loads from the aligned-down start
+        l0 = a.blk_lptr[vb] & ~7;
+        const uint32_t n16 = (uint32_t)(a.blk_lptr[vb + nvb] - l0 + 7) >> 3;
+        const uint4 *src = (const uint4 *)(a.blk_list + l0);
+        for (uint32_t i = tid; i < n16; i += nthr) s_dyn4[i] = src[i];
+    }
+    if (has) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_d[k * nvb + tid] = ldc<double>(a.d[k], gv0);
+            if (OP == OP_KMUL) s_u[k * nvb + tid] = ldc<double>(a.u[k], gv0);
+            if (RED == 1) s_acc[k * nvb + tid] = 0.0;
+        }
+    }
+    for (uint32_t i = tid + nthr; i < nvb; i += nthr) {
+        const uint32_t gv = (uint32_t)a.blk_verts[vb + i];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_d[k * nvb + i] = ldc<double>(a.d[k], gv);
+            if (OP == OP_KMUL) s_u[k * nvb + i] = ldc<double>(a.u[k], gv);
+            if (RED == 1) s_acc[k * nvb + i] = 0.0;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TPT; ++r) {
+        const uint32_t tl = r * nthr + tid, t = t0 + tl;
+        if (t < nt) {
+            double qd[4][3], qu[4][3];
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    qd[c][k] = s_d[k * nvb + slot[c]];
-                    qu[c][k] = (OP == OP_KMUL) ? s_u[k * nvb + slot[c]] : 0.0;
+                    qd[c][k] = s_d[k * nvb + sl[r][c]];
+                    qu[c][k] = (OP == OP_KMUL) ? s_u[k * nvb + sl[r][c]] : 0.0;
                 }
-        } else {
+            T h[12];
+            const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h);
+            if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv, 1ull);
+            if (RED == 0) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) v[c] = a.keys[c * nt + t];
+                for (int j = 0; j < 12; ++j) s_h[j * BT + tl] = h[j];
+            } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+                for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    qd[c][k] = a.d[k * nv + v[c]];
-                    qu[c][k] = (OP == OP_KMUL) ? a.u[k * nv + v[c]] : 0.0;
-                }
-        }
-        T h[12];
-        const bool ok = eval_tet<T, MODEL, OP>(mu, lam, b, V0, qd, qu, h);
-        if (MODEL == EBBX_NH && !ok && OP == OP_FORCE) atomicAdd(a.n_inv, 1ull);
-        if (SC == SC_ATOMIC) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) atomicAdd(&a.out[k * nv + v[c]], (double)h[3 * c + k]);
-        } else if (SC == SC_PART) {
-            T *pp = (T *)a.part + 12 * t;
-#pragma unroll
-            for (int k = 0; k < 12; ++k) pp[k] = h[k];
-        } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) atomicAdd(&s_acc[k * nvb + slot[c]], (double)h[3 * c + k]);
-        }
-    }
-
-    if (SC == SC_BLOCK) {
-        __syncthreads();
-        for (int i = threadIdx.x; i < nvb; i += blockDim.x) {
-            const int64_t gv = a.blk_verts[vbase + i];
-            const bool own = a.blk_own[vbase + i] != 0;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const double val = s_acc[k * nvb + i];
-                if (own)
-                    a.out[k * nv + gv] = val;   // sole writer; out was pre-set for accumulate
-                else
-                    atomicAdd(&a.out[k * nv + gv], val);
+                    for (int k = 0; k < 3; ++k) atomicAdd(&s_acc[k * nvb + sl[r][c]], (double)h[3 * c + k]);
             }
         }
+    }
+    __syncthreads();
+    if (RED == 0) {
+        if (has) reduce_slot<T>(a, s_list, s_h, BT, bsh, gv0, hp0, j00 - l0, j10 - l0);
+        for (uint32_t i = tid + nthr; i < nvb; i += nthr)
+            reduce_slot<T>(a, s_list, s_h, BT, bsh, (uint32_t)a.blk_verts[vb + i], a.blk_hpos[vb + i],
+                           a.blk_lptr[vb + i] - l0, a.blk_lptr[vb + i + 1] - l0);
+    } else {
+        for (uint32_t i = tid; i < nvb; i += nthr) {
+            const uint32_t gv = i == tid ? gv0 : (uint32_t)a.blk_verts[vb + i];
+            const int32_t hp = i == tid ? hp0 : a.blk_hpos[vb + i];
+            double v0 = s_acc[i], v1 = s_acc[nvb + i], v2 = s_acc[2 * nvb + i];
+            if (hp < 0) {
+                if (a.accumulate) {
+                    v0 += ldc<double>(a.out[0], gv);
+                    v1 += ldc<double>(a.out[1], gv);
+                    v2 += ldc<double>(a.out[2], gv);
+                }
+                stc<double>(a.out[0], gv, v0);
+                stc<double>(a.out[1], gv, v1);
+                stc<double>(a.out[2], gv, v2);
+            } else {
+                stc<double>(a.halo[0], (uint32_t)hp, v0);
+                stc<double>(a.halo[1], (uint32_t)hp, v1);
+                stc<double>(a.halo[2], (uint32_t)hp, v2);
+            }
+        }
+    }
+}
+
+// Sum each shared vertex's halo run (its blocks' partials, in block order).
+__global__ __launch_bounds__(256) void k_halo_reduce(const double *h0, const double *h1, const double *h2,
+                                                     const int32_t *sh_vert, const int32_t *sh_ptr, uint32_t S,
+                                                     double *o0, double *o1, double *o2, int accumulate,
+                                                     const int *skip) {
+    if (skip && *skip) return;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)sh_vert[s];
+        const int32_t j0 = sh_ptr[s], j1 = sh_ptr[s + 1];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int32_t j = j0; j < j1; ++j) {
+            a0 += ldc<double>(h0, (uint32_t)j);
+            a1 += ldc<double>(h1, (uint32_t)j);
+            a2 += ldc<double>(h2, (uint32_t)j);
+        }
+        if (accumulate) {
+            a0 += ldc<double>(o0, v);
+            a1 += ldc<double>(o1, v);
+            a2 += ldc<double>(o2, v);
+        }
+        stc<double>(o0, v, a0);
+        stc<double>(o1, v, a1);
+        stc<double>(o2, v, a2);
     }
 }
 
@@ -426,22 +632,6 @@ __global__ void k_fill(double *p, int64_t n, double v) {
         p[i] = v;
 }
 
-// Zero only the vertices the block strategy adds atomically into.
-__global__ void k_zero_shared(double *out, int64_t nv, const int32_t *verts, const uint8_t *own, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        if (!own[i]) {
-            const int64_t v = verts[i];
-            out[v] = 0.0;
-            out[nv + v] = 0.0;
-            out[2 * nv + v] = 0.0;
-        }
-}
-
-__global__ void k_axpy_inplace(double *y, const double *x, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        y[i] += x[i];
-}
-
 static unsigned grid_n(int64_t n, int threads, int64_t cap = 65536) {
     int64_t g = (n + threads - 1) / threads;
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>(g, cap));
@@ -453,49 +643,85 @@ void fill_f64(double *p, int64_t n, double v, hipStream_t s) {
     HIPCHK(hipGetLastError());
 }
 
-template <class T, int MODEL, int OP, int SC>
-static void launch_k(const ElemArgs &a, int block, size_t shmem, unsigned grid, hipStream_t s) {
-    hipLaunchKernelGGL((k_elem<T, MODEL, OP, SC>), dim3(grid), dim3(block), shmem, s, a);
+// ---- dispatch ---------------------------------------------------------------------------
+
+template <class T, int MODEL, int OP>
+static void launch_flat(int sc, const ElemArgs &a, int block, hipStream_t s) {
+    const unsigned grid = grid_n(a.nt, block, 1ll << 31);
+    if (sc == SC_ATOMIC) hipLaunchKernelGGL((k_elem<T, MODEL, OP, SC_ATOMIC>), dim3(grid), dim3(block), 0, s, a);
+    else hipLaunchKernelGGL((k_elem<T, MODEL, OP, SC_PART>), dim3(grid), dim3(block), 0, s, a);
+    HIPCHK(hipGetLastError());
+}
+
+template <class T, int MODEL, int OP, int W>
+static void launch_block_w(int tpt, int red, const ElemArgs &a, int threads, unsigned grid, size_t shmem,
+                           hipStream_t s) {
+    if (red == 0) {
+        if (tpt == 1) hipLaunchKernelGGL((k_block<T, MODEL, OP, 1, W, 0>), dim3(grid), dim3(threads), shmem, s, a);
+        else hipLaunchKernelGGL((k_block<T, MODEL, OP, 2, W, 0>), dim3(grid), dim3(threads), shmem, s, a);
+    } else {
+        if (tpt == 1) hipLaunchKernelGGL((k_block<T, MODEL, OP, 1, W, 1>), dim3(grid), dim3(threads), shmem, s, a);
+        else hipLaunchKernelGGL((k_block<T, MODEL, OP, 2, W, 1>), dim3(grid), dim3(threads), shmem, s, a);
+    }
     HIPCHK(hipGetLastError());
 }
 
 template <class T, int MODEL, int OP>
-static void launch_sc(int sc, const ElemArgs &a, int block, size_t shmem, unsigned grid, hipStream_t s) {
-    if (sc == SC_ATOMIC) launch_k<T, MODEL, OP, SC_ATOMIC>(a, block, shmem, grid, s);
-    else if (sc == SC_PART) launch_k<T, MODEL, OP, SC_PART>(a, block, shmem, grid, s);
-    else launch_k<T, MODEL, OP, SC_BLOCK>(a, block, shmem, grid, s);
+static void launch_block(int tpt, int w, int red, const ElemArgs &a, int threads, unsigned grid, size_t shmem,
+                         hipStream_t s) {
+    if (w == 1) launch_block_w<T, MODEL, OP, 1>(tpt, red, a, threads, grid, shmem, s);
+    else launch_block_w<T, MODEL, OP, 2>(tpt, red, a, threads, grid, shmem, s);
 }
 
-template <class T>
-static void launch_model_op(int model, ElemOp op, int sc, const ElemArgs &a, int block, size_t shmem, unsigned grid,
-                            hipStream_t s) {
-    if (model == EBBX_STVK) {
-        if (op == OP_FORCE) launch_sc<T, EBBX_STVK, OP_FORCE>(sc, a, block, shmem, grid, s);
-        else if (op == OP_KMUL) launch_sc<T, EBBX_STVK, OP_KMUL>(sc, a, block, shmem, grid, s);
-        else launch_sc<T, EBBX_STVK, OP_DIAG>(sc, a, block, shmem, grid, s);
+template <class T, int MODEL>
+static void launch_model(bool block, ElemOp op, int sc, int tpt, int w, int red, const ElemArgs &a, int threads,
+                         unsigned grid, size_t shmem, hipStream_t s) {
+    if (block) {
+        if (op == OP_FORCE) launch_block<T, MODEL, OP_FORCE>(tpt, w, red, a, threads, grid, shmem, s);
+        else if (op == OP_KMUL) launch_block<T, MODEL, OP_KMUL>(tpt, w, red, a, threads, grid, shmem, s);
+        else launch_block<T, MODEL, OP_DIAG>(tpt, w, red, a, threads, grid, shmem, s);
     } else {
-        if (op == OP_FORCE) launch_sc<T, EBBX_NH, OP_FORCE>(sc, a, block, shmem, grid, s);
-        else if (op == OP_KMUL) launch_sc<T, EBBX_NH, OP_KMUL>(sc, a, block, shmem, grid, s);
-        else launch_sc<T, EBBX_NH, OP_DIAG>(sc, a, block, shmem, grid, s);
+        if (op == OP_FORCE) launch_flat<T, MODEL, OP_FORCE>(sc, a, threads, s);
+        else if (op == OP_KMUL) launch_flat<T, MODEL, OP_KMUL>(sc, a, threads, s);
+        else launch_flat<T, MODEL, OP_DIAG>(sc, a, threads, s);
     }
 }
 
 static ElemArgs base_args(ebbx_fem_s *F) {
     ElemArgs a{};
-    a.nt = F->nt;
-    a.nv = F->nv;
-    a.keys = F->keys;
-    a.B = F->B.get();
+    const uint32_t nt = (uint32_t)F->nt, nv = (uint32_t)F->nv;
+    const size_t es = F->esize;
+    a.nt = nt;
+    a.nv = nv;
+    for (int c = 0; c < 4; ++c) a.key[c] = F->keys + (size_t)c * nt;
+    for (int k = 0; k < 9; ++k) a.B[k] = (const char *)F->B.get() + (size_t)k * nt * es;
     a.V0 = F->V0.get();
-    a.mat = F->per_tet ? F->mat.get() : nullptr;
+    if (F->per_tet) {
+        a.mu_t = F->mat.get();
+        a.lam_t = (const char *)F->mat.get() + (size_t)nt * es;
+    }
     a.mu = F->mu;
     a.lam = F->lam;
     a.n_inv = F->status.as<unsigned long long>();
     a.blk_vptr = F->blk_vptr.as<int32_t>();
     a.blk_verts = F->blk_verts.as<int32_t>();
-    a.blk_own = F->blk_own.as<uint8_t>();
-    a.blk_local = F->blk_local.as<uint16_t>();
+    a.blk_lptr = F->blk_lptr.as<int32_t>();
+    a.blk_list = F->blk_list.as<uint16_t>();
+    a.blk_hpos = F->blk_hpos.as<int32_t>();
+    a.slot[0] = F->blk_local.as<uint32_t>();
+    a.slot[1] = F->blk_local.as<uint32_t>() + (F->blk_w == 2 ? nt : 0);
+    for (int k = 0; k < 3; ++k) a.halo[k] = F->halo.as<double>() + (size_t)k * F->halo_n;
     return a;
+}
+
+static void set_vec(const double *(&dst)[3], const double *p, uint32_t nv) {
+    for (int k = 0; k < 3; ++k) dst[k] = p ? p + (size_t)k * nv : nullptr;
+}
+
+size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
+    const size_t stage = (size_t)3 * (op == OP_KMUL ? 2 : 1) * F->blk_maxv * sizeof(double);
+    if (F->blk_red == 1) return stage + (size_t)3 * F->blk_maxv * sizeof(double);
+    return (size_t)8 * F->blk_tets + 16 + stage + (size_t)12 * F->blk_tets * F->esize;
 }
 
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
@@ -507,40 +733,47 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
         return;
     }
     ElemArgs a = base_args(F);
-    a.d = d;
-    a.u = u;
-    a.out = out;
+    set_vec(a.d, d, (uint32_t)nv);
+    set_vec(a.u, u, (uint32_t)nv);
+    for (int k = 0; k < 3; ++k) a.out[k] = out + (size_t)k * nv;
     a.part = F->part.get();
     a.skip = skip;
-    const int sc = F->strategy == EBBX_STRAT_SEG ? SC_PART : F->strategy == EBBX_STRAT_BLOCK ? SC_BLOCK : SC_ATOMIC;
-    int block = F->block > 0 ? F->block : 256;
-    size_t shmem = 0;
-    unsigned grid = grid_n(nt, block, 1ll << 31);
-    double *target = out;
-    if (sc == SC_BLOCK) {
-        block = F->blk_tets;
-        grid = (unsigned)F->nblk;
-        const int nq = (op == OP_KMUL) ? 2 : 1;
-        shmem = (size_t)3 * (nq + 1) * F->blk_maxv * sizeof(double);
+    a.accumulate = accumulate;
+    if (F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS) {
+        const size_t shmem = block_shmem(F, op);
         if (shmem > 64 * 1024)
             fail(EBBX_E_STATE, "block strategy needs %zu bytes of LDS per block (%d vertices); reorder the mesh "
-                 "(Morton) or use a smaller block", shmem, F->blk_maxv);
-        if (accumulate) {
-            // owned vertices are stored, not added: reduce into zeroed scratch, then add
-            target = F->scratch.as<double>();
-            a.out = target;
-            fill_f64(target, 3 * nv, 0.0, s);
+                 "(Morton) or use smaller blocks", shmem, F->blk_maxv);
+        const int threads = std::min(F->blk_tets, 256), tpt = F->blk_tets / threads;
+        if (tpt > 2) fail(EBBX_E_ARG, "block strategy: at most 512 tets per block");
+        const unsigned grid = (unsigned)F->nblk;
+        if (F->prec == EBBX_F32) {
+            if (F->model == EBBX_STVK) launch_model<float, EBBX_STVK>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
+            else launch_model<float, EBBX_NH>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
         } else {
-            // zero what is added atomically (shared and isolated vertices)
-            hipLaunchKernelGGL(k_zero_shared, dim3(grid_n(F->blk_nverts, 256, 8192)), dim3(256), 0, s, target, nv,
-                               F->blk_verts.as<int32_t>(), F->blk_own.as<uint8_t>(), F->blk_nverts);
+            if (F->model == EBBX_STVK) launch_model<double, EBBX_STVK>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
+            else launch_model<double, EBBX_NH>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
+        }
+        if (F->sh_n > 0) {
+            const double *h = F->halo.as<double>();
+            const size_t hn = (size_t)F->halo_n;
+            hipLaunchKernelGGL(k_halo_reduce, dim3(grid_n(F->sh_n, 256, 1ll << 20)), dim3(256), 0, s, h, h + hn,
+                               h + 2 * hn, F->sh_vert.as<int32_t>(), F->sh_ptr.as<int32_t>(), (uint32_t)F->sh_n,
+                               out, out + nv, out + 2 * nv, accumulate, skip);
             HIPCHK(hipGetLastError());
         }
-    } else if (sc == SC_ATOMIC && !accumulate) {
-        fill_f64(out, 3 * nv, 0.0, s);
+        return;
     }
-    if (F->prec == EBBX_F32) launch_model_op<float>(F->model, op, sc, a, block, shmem, grid, s);
-    else launch_model_op<double>(F->model, op, sc, a, block, shmem, grid, s);
+    const int sc = F->strategy == EBBX_STRAT_SEG ? SC_PART : SC_ATOMIC;
+    const int threads = F->block > 0 ? F->block : 256;
+    if (sc == SC_ATOMIC && !accumulate) fill_f64(out, 3 * nv, 0.0, s);
+    if (F->prec == EBBX_F32) {
+        if (F->model == EBBX_STVK) launch_model<float, EBBX_STVK>(false, op, sc, 1, 1, 0, a, threads, 0, 0, s);
+        else launch_model<float, EBBX_NH>(false, op, sc, 1, 1, 0, a, threads, 0, 0, s);
+    } else {
+        if (F->model == EBBX_STVK) launch_model<double, EBBX_STVK>(false, op, sc, 1, 1, 0, a, threads, 0, 0, s);
+        else launch_model<double, EBBX_NH>(false, op, sc, 1, 1, 0, a, threads, 0, 0, s);
+    }
     if (sc == SC_PART) {
         const unsigned g = grid_n(nv, 256, 1ll << 31);
         if (F->prec == EBBX_F32)
@@ -551,11 +784,6 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
                                F->group->row_ptr.as<int64_t>(), F->group->inc.as<int32_t>(), nv, out, accumulate);
         HIPCHK(hipGetLastError());
     }
-    if (sc == SC_BLOCK && accumulate) {
-        hipLaunchKernelGGL(k_axpy_inplace, dim3(grid_n(3 * nv, 256, 8192)), dim3(256), 0, s, out,
-                           (const double *)target, 3 * nv);
-        HIPCHK(hipGetLastError());
-    }
 }
 
 // ---- energy ------------------------------------------------------------------------------
@@ -563,21 +791,21 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
 template <class T, int MODEL>
 __global__ __launch_bounds__(256) void k_energy(ElemArgs a, double *part) {
     __shared__ double s_w[4];
-    const int64_t nt = a.nt, nv = a.nv;
+    const uint32_t nt = a.nt;
     double acc = 0.0;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
         double b[9];
-        for (int k = 0; k < 9; ++k) b[k] = (double)((const T *)a.B)[k * nt + t];
-        const double V0 = (double)((const T *)a.V0)[t];
+        for (int k = 0; k < 9; ++k) b[k] = (double)ldc<T>(a.B[k], t);
+        const double V0 = (double)ldc<T>(a.V0, t);
         double mu = a.mu, lam = a.lam;
-        if (a.mat) {
-            mu = (double)((const T *)a.mat)[t];
-            lam = (double)((const T *)a.mat)[nt + t];
+        if (a.mu_t) {
+            mu = (double)ldc<T>(a.mu_t, t);
+            lam = (double)ldc<T>(a.lam_t, t);
         }
         double q[4][3];
         for (int c = 0; c < 4; ++c) {
-            const int64_t v = a.keys[c * nt + t];
-            for (int k = 0; k < 3; ++k) q[c][k] = a.d[k * nv + v];
+            const uint32_t v = (uint32_t)ldc<int32_t>(a.key[c], t);
+            for (int k = 0; k < 3; ++k) q[c][k] = ldc<double>(a.d[k], v);
         }
         double G[9];
         grad_from(q, b, G);
@@ -621,9 +849,9 @@ __global__ void k_sum_parts(const double *part, int n, double *out) {
 
 void elem_energy(ebbx_fem_s *F, const double *d, double *out_dev, hipStream_t s) {
     ElemArgs a = base_args(F);
-    a.d = d;
+    set_vec(a.d, d, (uint32_t)F->nv);
     const unsigned g = 1024;
-    double *part = F->scratch.as<double>();   // scratch holds >= 3 nv >= 1024 doubles
+    double *part = F->scratch.as<double>();   // scratch holds >= 4096 doubles
     if (F->prec == EBBX_F32) {
         if (F->model == EBBX_STVK) hipLaunchKernelGGL((k_energy<float, EBBX_STVK>), dim3(g), dim3(256), 0, s, a, part);
         else hipLaunchKernelGGL((k_energy<float, EBBX_NH>), dim3(g), dim3(256), 0, s, a, part);
@@ -720,31 +948,37 @@ int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hip
 
 // ---- block tables -----------------------------------------------------------------------
 
-// Tets are cut into blocks of blk_tets consecutive rows.  Per block: the sorted
-// set of vertices it touches, each corner's slot in that set, and whether the
-// block holds every incident tet of a vertex (then it is the vertex's only
-// writer and stores instead of adding atomically).
-void build_blocks(ebbx_fem_s *F, hipStream_t s) {
+// Tets are cut into blocks of bt consecutive rows.  Per block: the sorted set of
+// vertices it touches, each corner's slot in that set, each vertex's incidence
+// list inside the block (entries c * bt + local tet, ordered by local tet then
+// corner), and where its partial sum goes: nowhere else if the block holds
+// every incident tet of the vertex (the block stores it), otherwise a halo
+// position.  Halo positions are grouped by vertex, in block order; vertices
+// that no tet touches get an empty run, so the halo pass zeroes them.
+void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
     const int64_t nt = F->nt, nv = F->nv;
-    const int bt = F->block > 0 ? F->block : 256;
-    F->blk_tets = bt;
-    F->nblk = (nt + bt - 1) / bt;
+    if (bt != 64 && bt != 128 && bt != 256 && bt != 512 && bt != 1024)
+        fail(EBBX_E_ARG, "block strategy: tets per block must be 64, 128, 256, 512 or 1024 (got %d)", bt);
+    const int64_t nblk = (nt + bt - 1) / bt;
     std::vector<int32_t> keys((size_t)(4 * nt));
     if (nt > 0) HIPCHK(hipMemcpy(keys.data(), F->keys, keys.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     std::vector<int64_t> rp((size_t)(nv + 1));
     HIPCHK(hipMemcpy(rp.data(), F->group->row_ptr.get(), rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-    std::vector<int32_t> vptr((size_t)F->nblk + 2, 0), verts;
+    std::vector<int32_t> vptr((size_t)nblk + 1, 0), verts, lptr(1, 0);
+    std::vector<uint16_t> list;
     std::vector<uint8_t> own;
     std::vector<uint16_t> local((size_t)(4 * nt));
     verts.reserve((size_t)(nt + 16));
     own.reserve((size_t)(nt + 16));
-    std::vector<std::pair<int32_t, int32_t>> buf;   // (vertex, corner index in block)
+    lptr.reserve((size_t)(nt + 16));
+    list.reserve((size_t)(4 * nt));
+    std::vector<std::pair<int32_t, int32_t>> buf;   // (vertex, local tet * 4 + corner)
     int32_t maxv = 1;
-    for (int64_t b = 0; b < F->nblk; ++b) {
+    for (int64_t b = 0; b < nblk; ++b) {
         const int64_t t0 = b * bt, t1 = std::min<int64_t>(nt, t0 + bt);
         buf.clear();
         for (int64_t t = t0; t < t1; ++t)
-            for (int c = 0; c < 4; ++c) buf.push_back({keys[(size_t)(c * nt + t)], (int32_t)(c * bt + (t - t0))});
+            for (int c = 0; c < 4; ++c) buf.push_back({keys[(size_t)(c * nt + t)], (int32_t)(4 * (t - t0) + c)});
         std::sort(buf.begin(), buf.end());
         int32_t nb = 0;
         size_t i = 0;
@@ -753,38 +987,73 @@ void build_blocks(ebbx_fem_s *F, hipStream_t s) {
             while (j < buf.size() && buf[j].first == buf[i].first) ++j;
             const int32_t v = buf[i].first;
             for (size_t k = i; k < j; ++k) {
-                const int c = buf[k].second / bt, tl = buf[k].second % bt;
+                const int32_t tl = buf[k].second >> 2, c = buf[k].second & 3;
                 local[(size_t)(c * nt + t0 + tl)] = (uint16_t)nb;
+                list.push_back((uint16_t)(c * bt + tl));
             }
             verts.push_back(v);
+            lptr.push_back((int32_t)list.size());
             own.push_back((int64_t)(j - i) == rp[(size_t)v + 1] - rp[(size_t)v] ? 1 : 0);
             ++nb;
             i = j;
         }
         maxv = std::max(maxv, nb);
         vptr[(size_t)b + 1] = (int32_t)verts.size();
+        if (verts.size() >= (size_t)(1u << 31)) fail(EBBX_E_ARG, "block tables exceed int32");
     }
-    if (maxv > 65535) fail(EBBX_E_ARG, "block touches %d vertices (limit 65535)", maxv);
-    vptr[(size_t)F->nblk + 1] = maxv;
-    // vertices no tet touches: listed after the blocks as shared, so that they are zeroed
-    for (int64_t v = 0; v < nv; ++v)
-        if (rp[(size_t)v + 1] == rp[(size_t)v]) {
-            verts.push_back((int32_t)v);
-            own.push_back(0);
+    if (maxv > 65535) fail(EBBX_E_ARG, "a block touches %d vertices (limit 65535)", maxv);
+    // the kernel copies each block's list with 16-byte loads from the aligned-down
+    // start, so the array carries 8 entries of tail padding that nothing references
+    for (int k = 0; k < 8; ++k) list.push_back(0);
+    // packed slots: 4 x 8 bits per word if every block has <= 256 vertices
+    const int w = maxv <= 256 ? 1 : 2;
+    std::vector<uint32_t> packed((size_t)(w * std::max<int64_t>(nt, 1)), 0u);
+    for (int64_t t = 0; t < nt; ++t) {
+        const uint32_t s0 = local[(size_t)t], s1 = local[(size_t)(nt + t)], s2 = local[(size_t)(2 * nt + t)],
+                       s3 = local[(size_t)(3 * nt + t)];
+        if (w == 1) {
+            packed[(size_t)t] = s0 | (s1 << 8) | (s2 << 16) | (s3 << 24);
+        } else {
+            packed[(size_t)t] = s0 | (s1 << 16);
+            packed[(size_t)(nt + t)] = s2 | (s3 << 16);
         }
-    F->blk_maxv = maxv;
-    F->blk_nverts = (int64_t)verts.size();
-    F->blk_vptr.reset(vptr.size() * sizeof(int32_t), s);
-    F->blk_verts.reset(std::max<size_t>(verts.size(), 1) * sizeof(int32_t), s);
-    F->blk_own.reset(std::max<size_t>(own.size(), 1), s);
-    F->blk_local.reset(std::max<size_t>(local.size(), 1) * sizeof(uint16_t), s);
-    HIPCHK(hipMemcpy(F->blk_vptr.get(), vptr.data(), vptr.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-    if (!verts.empty()) {
-        HIPCHK(hipMemcpy(F->blk_verts.get(), verts.data(), verts.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(F->blk_own.get(), own.data(), own.size(), hipMemcpyHostToDevice));
     }
-    if (!local.empty())
-        HIPCHK(hipMemcpy(F->blk_local.get(), local.data(), local.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+    // halo: runs per shared (or untouched) vertex, in vertex order, entries in block order
+    std::vector<int32_t> count((size_t)nv, 0);
+    for (size_t p = 0; p < verts.size(); ++p)
+        if (!own[p]) ++count[(size_t)verts[p]];
+    std::vector<int32_t> sh_vert, sh_ptr(1, 0), start((size_t)nv, -1);
+    for (int64_t v = 0; v < nv; ++v) {
+        const bool isolated = rp[(size_t)v + 1] == rp[(size_t)v];
+        if (count[(size_t)v] > 0 || isolated) {
+            start[(size_t)v] = sh_ptr.back();
+            sh_vert.push_back((int32_t)v);
+            sh_ptr.push_back(sh_ptr.back() + count[(size_t)v]);
+        }
+    }
+    std::vector<int32_t> hpos(verts.size(), -1);
+    for (size_t p = 0; p < verts.size(); ++p)
+        if (!own[p]) hpos[p] = start[(size_t)verts[p]]++;
+    F->blk_tets = bt;
+    F->nblk = nblk;
+    F->blk_maxv = maxv;
+    F->blk_w = w;
+    F->blk_nverts = (int64_t)verts.size();
+    F->sh_n = (int64_t)sh_vert.size();
+    F->halo_n = (int64_t)sh_ptr.back();
+    auto up = [&](DevBuf &dst, const void *src, size_t bytes) {
+        dst.reset(std::max<size_t>(bytes, 8), s);
+        if (bytes) HIPCHK(hipMemcpy(dst.get(), src, bytes, hipMemcpyHostToDevice));
+    };
+    up(F->blk_vptr, vptr.data(), vptr.size() * sizeof(int32_t));
+    up(F->blk_verts, verts.data(), verts.size() * sizeof(int32_t));
+    up(F->blk_lptr, lptr.data(), lptr.size() * sizeof(int32_t));
+    up(F->blk_list, list.data(), list.size() * sizeof(uint16_t));
+    up(F->blk_hpos, hpos.data(), hpos.size() * sizeof(int32_t));
+    up(F->blk_local, packed.data(), packed.size() * sizeof(uint32_t));
+    up(F->sh_vert, sh_vert.data(), sh_vert.size() * sizeof(int32_t));
+    up(F->sh_ptr, sh_ptr.data(), sh_ptr.size() * sizeof(int32_t));
+    F->halo.reset(std::max<size_t>((size_t)F->halo_n * 3 * sizeof(double), 8), s);
     F->blocks_built = true;
 }
 

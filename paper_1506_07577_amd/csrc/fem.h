@@ -9,24 +9,30 @@ namespace ebbx {
 
 enum ElemOp { OP_FORCE = 0, OP_KMUL = 1, OP_DIAG = 2 };
 
-// Everything an element kernel reads; plain pointers, passed by value.
+// Everything an element kernel reads; plain pointers, passed by value.  Column
+// stores are passed as one base pointer per component, so that a kernel
+// addresses every column of a row with one 32-bit byte offset.
 struct ElemArgs {
-    int64_t nt, nv;
-    const int32_t *keys;   // (4, nt) int32 key-field tets.v
-    const void *B;         // (9, nt) element precision, B = Dm^-1 row-major
-    const void *V0;        // (nt) element precision
-    const void *mat;       // (2, nt) element precision (mu, lam) or NULL
-    double mu, lam;        // uniform material when mat == NULL
-    const double *d;       // (3, nv) displacement
-    const double *u;       // (3, nv) direction (stiffness product)
-    double *out;           // (3, nv) reduce target (atomic / block strategies)
-    void *part;            // (nt, 12) element precision per-corner partials (segmented)
+    uint32_t nt, nv;
+    const int32_t *key[4];      // columns of the key-field tets.v
+    const void *B[9];           // columns of B = Dm^-1 (row-major entries), element precision
+    const void *V0;             // (nt) element precision
+    const void *mu_t, *lam_t;   // per-tet Lame parameters (element precision) or NULL
+    double mu, lam;             // uniform material when mu_t == NULL
+    const double *d[3];         // displacement columns
+    const double *u[3];         // direction columns (stiffness product)
+    double *out[3];             // reduce target columns
+    void *part;                 // (nt, 12) per-corner partials (segmented reduction)
     unsigned long long *n_inv;  // inverted-element counter
     // block strategy
     const int32_t *blk_vptr;    // (nblk + 1) offsets into blk_verts
     const int32_t *blk_verts;   // global vertex ids per block, sorted
-    const uint8_t *blk_own;     // 1 if every incident tet of that vertex is in the block
-    const uint16_t *blk_local;  // (4, nt) local slot of each corner within its block
+    const int32_t *blk_lptr;    // per block vertex: [lptr[i], lptr[i+1]) in blk_list
+    const uint16_t *blk_list;   // incidences c*BT + local tet of each block vertex, fixed order
+    const int32_t *blk_hpos;    // per block vertex: halo position, or -1 if the block owns it
+    const uint32_t *slot[2];    // packed corner slots within the block (one or two words per tet)
+    double *halo[3];            // partial sums of shared vertices, per component
+    int accumulate;             // 1: out += result
     const int *skip;            // nullable device flag: nonzero = return at once (converged solve)
 };
 
@@ -42,7 +48,7 @@ int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hip
 // Fill n doubles with a value (graph-safe, no memset node).
 void fill_f64(double *p, int64_t n, double v, hipStream_t s);
 // Build the tet-block tables of the BLOCK strategy.
-void build_blocks(ebbx_fem_s *F, hipStream_t s);
+void build_blocks(ebbx_fem_s *F, int32_t tets_per_block, hipStream_t s);
 
 }  // namespace ebbx
 
@@ -62,8 +68,12 @@ struct ebbx_fem_s {
     int32_t blk_tets = 0;      // tets per block
     int64_t nblk = 0;
     int32_t blk_maxv = 0;      // largest vertex count of one block
-    int64_t blk_nverts = 0;    // entries of blk_verts (block lists, then isolated vertices)
-    ebbx::DevBuf blk_vptr, blk_verts, blk_own, blk_local;
+    int32_t blk_w = 1;         // 32-bit words of packed corner slots per tet
+    int32_t blk_red = 0;       // 0: incidence-list sums (deterministic), 1: FP64 LDS atomics
+    int64_t blk_nverts = 0;    // entries of blk_verts over all blocks
+    int64_t sh_n = 0;          // vertices summed from the halo (shared or untouched)
+    int64_t halo_n = 0;        // halo entries
+    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_list, blk_hpos, blk_local, halo, sh_vert, sh_ptr;
     bool blocks_built = false;
 
     // implicit-step state (allocated on first step)

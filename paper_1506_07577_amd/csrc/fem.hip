@@ -287,20 +287,26 @@ bool overlap(const void *a, const void *b, size_t bytes) {
     return x < y + bytes && y < x + bytes;
 }
 
+// `block`: threads per workgroup for ATOMIC and SEG (64..256, multiple of 64);
+// tets per block for BLOCK (64, 128, 256, 512 or 1024).  0 = default.
 void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s) {
-    if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_BLOCK) fail(EBBX_E_ARG, "bad strategy %d", strategy);
+    if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_BLOCK_LDS) fail(EBBX_E_ARG, "bad strategy %d", strategy);
+    if (strategy == EBBX_STRAT_AUTO) strategy = EBBX_STRAT_BLOCK;
+    if (strategy == EBBX_STRAT_BLOCK || strategy == EBBX_STRAT_BLOCK_LDS) {
+        const int32_t bt = block ? block : 256;
+        if (bt > 512) fail(EBBX_E_ARG, "block strategies take at most 512 tets per block");
+        if (!F->blocks_built || F->blk_tets != bt) build_blocks(F, bt, s);
+        F->strategy = strategy;
+        F->blk_red = strategy == EBBX_STRAT_BLOCK_LDS ? 1 : 0;
+        F->block = bt;
+        return;
+    }
     if (block != 0 && (block < 64 || block > 256 || block % 64))
         fail(EBBX_E_ARG, "block %d must be a multiple of 64 in [64, 256]", block);
-    if (strategy == EBBX_STRAT_AUTO) strategy = EBBX_STRAT_ATOMIC;
-    const int32_t blk = block ? block : 256;
     if (strategy == EBBX_STRAT_SEG && !F->part.get())
         F->part.reset((size_t)std::max<int64_t>(F->nt, 1) * 12 * F->esize, s);
-    if (strategy == EBBX_STRAT_BLOCK && (!F->blocks_built || F->blk_tets != blk)) {
-        F->block = blk;
-        build_blocks(F, s);
-    }
     F->strategy = strategy;
-    F->block = blk;
+    F->block = block ? block : 256;
 }
 
 }  // namespace
@@ -327,6 +333,9 @@ ebbx_status ebbx_fem_create(ebbx_relation tets, const char *keyfield, ebbx_relat
     if (params->elem_prec != EBBX_F32 && params->elem_prec != EBBX_F64) fail(EBBX_E_DTYPE, "elem_prec must be F32 or F64");
     if (!(params->rho > 0.0)) fail(EBBX_E_ARG, "rho must be > 0");
     if (!(params->nu > -1.0 && params->nu < 0.5)) fail(EBBX_E_ARG, "nu must be in (-1, 0.5)");
+    // kernels address columns with 32-bit byte offsets (8-byte elements)
+    if (tr->size >= (int64_t(1) << 29) || vr->size >= (int64_t(1) << 29))
+        fail(EBBX_E_ARG, "FEM relations are limited to 2^29 rows");
     hipStream_t s = nullptr;
     std::unique_ptr<ebbx_fem_s> F(new ebbx_fem_s());
     F->tets = tr;
@@ -599,9 +608,14 @@ extern "C" ebbx_status ebbx_stats_fetch(const ebbx_step_stats *stats_dev, ebbx_s
 // ---- cache flush ---------------------------------------------------------------------------
 
 namespace {
-__global__ void k_flush(double *p, int64_t n) {
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = p[i] * 0.5 + 1.0;
+// Reads the buffer (clean lines only, so the next kernel does not pay for write-backs).
+__global__ void k_flush(const double4 *p, int64_t n, double *sink) {
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double4 v = p[i];
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    if (acc != 0.0) sink[0] = acc;   // the buffer is zero: never taken
 }
 std::mutex g_flush_mu;
 std::map<int, std::pair<void *, size_t>> g_flush_buf;   // per device, kept until the process ends
@@ -619,14 +633,14 @@ extern "C" ebbx_status ebbx_cache_flush(size_t bytes, ebbx_stream stream) {
             if (e.first) HIPCHK(hipFree(e.first));
             e.first = nullptr;
             e.second = 0;
-            HIPCHK(hipMalloc(&e.first, bytes));
-            HIPCHK(hipMemset(e.first, 0, bytes));
+            HIPCHK(hipMalloc(&e.first, bytes + 64));
+            HIPCHK(hipMemset(e.first, 0, bytes + 64));
             e.second = bytes;
         }
         p = e.first;
     }
-    const int64_t n = (int64_t)(bytes / sizeof(double));
-    hipLaunchKernelGGL(k_flush, dim3(8192), dim3(256), 0, (hipStream_t)stream, (double *)p, n);
+    const int64_t n = (int64_t)(bytes / sizeof(double4));
+    hipLaunchKernelGGL(k_flush, dim3(8192), dim3(256), 0, (hipStream_t)stream, (const double4 *)p, n, (double *)p);
     HIPCHK(hipGetLastError());
     EBBX_API_END
 }

@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/ebbx.h"
+#include "ebbx.h"
 
 namespace ebbx {
 

@@ -19,11 +19,12 @@ else:  # collected on a CPU host only to be deselected
     ebbx = None
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
-STRATS = ["atomic", "seg", "block"]
+STRATS = ["atomic", "seg", "block", "block_lds"]
 
 
 def _strat(name):
-    return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK}[name]
+    return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
+            "block_lds": ebbx.STRAT_BLOCK_LDS}[name]
 
 
 def _prec(p):
@@ -203,9 +204,10 @@ def test_morton_reordered_mesh_same_physics():
     mesh.fem.close()
 
 
-def test_seg_strategy_bitwise_reproducible():
+@pytest.mark.parametrize("strat", ["seg", "block"])
+def test_deterministic_strategies_bitwise_reproducible(strat):
     m = _mesh_small()
-    mesh, _ = _pair(m, 1, "f32", "seg")
+    mesh, _ = _pair(m, 1, "f32", strat, morton=True)
     d = mesh.to_dev(mg.perturbed_state(m, 0.02, seed=10))
     u = mesh.to_dev(mg.direction(m, 11))
     a = mesh.fem.kmul(d, u).clone()
