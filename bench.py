@@ -3,18 +3,21 @@
 
 Workload: 64^3 unit cube, 6 Kuhn tets per cell (1,572,864 tets, 274,625
 vertices), compressible neo-Hookean, E=1e6, nu=0.45, FP32 element arithmetic
-with FP64 vertex vectors, at a perturbed state d ~ U(+-0.02h) (seed 10) and
-direction u ~ U(-1,1) (seed 11).  Synthetic inputs stand in for the paper's
-meshes (Vega's dragon/hose/turtle and the FreeFem++ bunny are not available).
+with FP64 vertex vectors and FP64 accumulation, at a perturbed state
+d ~ U(+-0.02h) (seed 10) and direction u ~ U(-1,1) (seed 11), mesh in Morton
+order.  Synthetic inputs stand in for the paper's meshes (Vega's
+dragon/hose/turtle and the FreeFem++ bunny are not available).
 
 One step = one internal-force call + one stiffness-product call over the whole
-mesh.  Headline (cold): the device caches, including the 256 MB Infinity
-Cache, are flushed before each call, so the inputs come from HBM; each call is
-timed with HIP events on its stream.  value = tets / (t_force + t_Kmul).
-Also reported: the warm back-to-back rate, the implicit step (100 CG
-iterations), the roofline of the dominant call and the CPU oracle baseline.
+mesh.  Headline (cold): before each call a 1 GiB read-only stream evicts the
+device caches (including the 256 MB Infinity Cache), so the call's inputs come
+from HBM; each call is timed with HIP events on its stream and
+value = tets / mean(t_force + t_Kmul).  Also reported: the warm rate (steps
+back to back, timed as a whole), the implicit step (100 CG iterations), the
+roofline of the dominant call and the CPU oracle baseline.
 """
 import argparse
+import hashlib
 import json
 import os
 import statistics
@@ -25,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_cube64_nh_f32.json")
 
 
 def canonical_bytes(nt, nv, op, prec_bytes=4):
@@ -36,6 +40,14 @@ def canonical_bytes(nt, nv, op, prec_bytes=4):
     return nt * per_tet + nv * per_vert
 
 
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("elem.hip", "fem.hip", "fem.h"):
+        with open(os.path.join(ROOT, "paper_1506_07577_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,12 +56,14 @@ def parse():
     ap.add_argument("--strategy", default="block", choices=["atomic", "seg", "block", "block_lds"])
     ap.add_argument("--order", default="morton", choices=["lattice", "morton"])
     ap.add_argument("--n", type=int, default=64)
+    ap.add_argument("--block", type=int, default=0,
+                    help="tets per block (block strategies) or threads per workgroup (others); 0 = default")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-step", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--all-strategies", action="store_true")
-    ap.add_argument("--block", type=int, default=0,
-                    help="tets per block (block strategy) or threads per workgroup (others); 0 = default")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (counter calibration)")
     return ap.parse_args()
 
 
@@ -59,7 +73,6 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
     import torch
 
     from paper_1506_07577_amd import ebbx
@@ -69,7 +82,6 @@ def main():
         from paper_1506_07577_amd import build as hb
         hb.build()
     torch.cuda.set_device(0)
-    dev = torch.device("cuda:0")
     w = mg.workload_plain(args.n)
     m = w.mesh
     strat_id = {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
@@ -87,6 +99,12 @@ def main():
     y = torch.empty_like(d)
     stream = torch.cuda.current_stream()
     flush_bytes = 1 << 30
+    if args.calib_copy:
+        a = torch.zeros(1 << 25, dtype=torch.float64, device="cuda")   # 256 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def cold_run(steps):
         ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
@@ -103,70 +121,68 @@ def main():
             ev[k][3].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        tf = [e[0].elapsed_time(e[1]) for e in ev]
-        tk = [e[2].elapsed_time(e[3]) for e in ev]
-        return tf, tk, wall
+        return [e[0].elapsed_time(e[1]) for e in ev], [e[2].elapsed_time(e[3]) for e in ev], wall
 
     def warm_run(steps):
-        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+        # steps back to back, one event pair around all of them
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for k in range(steps):
-            ev[k][0].record(stream)
+        e0.record(stream)
+        for _ in range(steps):
             fem.forces(d, f, stream=stream)
-            ev[k][1].record(stream)
             fem.kmul(d, u, y, stream=stream)
-            ev[k][2].record(stream)
+        e1.record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        tf = [e[0].elapsed_time(e[1]) for e in ev]
-        tk = [e[1].elapsed_time(e[2]) for e in ev]
-        return tf, tk, wall
+        return e0.elapsed_time(e1) / steps
 
-    def measure(strategy):
-        fem.set_strategy(strat_id[strategy], args.block if strategy == args.strategy else 0)
+    def measure(strategy, block):
+        fem.set_strategy(strat_id[strategy], block)
         cold_run(max(args.warmup, 1))
         tf, tk, wall = cold_run(args.steps)
-        wtf, wtk, wwall = warm_run(args.steps)
-        return dict(tf=tf, tk=tk, wall=wall, wtf=wtf, wtk=wtk, wwall=wwall)
+        warm_ms = warm_run(args.steps)
+        return dict(tf=tf, tk=tk, wall=wall, warm_ms=warm_ms)
 
     others = {}
     if args.all_strategies:
         for s in ["atomic", "seg", "block", "block_lds"]:
             if s != args.strategy:
-                r = measure(s)
-                others[s] = {
-                    "cold_force_us": round(1e3 * statistics.median(r["tf"]), 2),
-                    "cold_kmul_us": round(1e3 * statistics.median(r["tk"]), 2),
-                    "warm_force_us": round(1e3 * statistics.median(r["wtf"]), 2),
-                    "warm_kmul_us": round(1e3 * statistics.median(r["wtk"]), 2),
-                }
-    r = measure(args.strategy)
+                r = measure(s, 0)
+                others[s] = {"cold_force_us": round(1e3 * statistics.median(r["tf"]), 2),
+                             "cold_kmul_us": round(1e3 * statistics.median(r["tk"]), 2),
+                             "warm_step_us": round(1e3 * r["warm_ms"], 2)}
+    r = measure(args.strategy, args.block)
     tf_ms = statistics.mean(r["tf"])
     tk_ms = statistics.mean(r["tk"])
     ms_per_step = tf_ms + tk_ms
     value = nt / (ms_per_step * 1e-3)
-    med_f, med_k = statistics.median(r["tf"]), statistics.median(r["tk"])
-    warm_ms = statistics.mean(r["wtf"]) + statistics.mean(r["wtk"])
 
     # roofline of the dominant call (the stiffness product): algorithmic bytes / mean duration
     bk = canonical_bytes(nt, nv, "kmul")
     bf = canonical_bytes(nt, nv, "force")
     achieved = bk / (tk_ms * 1e-3) / 1e9
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            tr = json.load(fh)
+        key = f"{args.strategy}_{args.order}_{fem.get_strategy()[1]}"
+        if tr.get("source_hash") == kernel_source_hash() and args.n == 64 and key in tr.get("kmul_bytes", {}):
+            traffic = tr["kmul_bytes"][key]
+    except (OSError, ValueError):
+        pass
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "stiffness product call (ebbx_fem_Kmul)",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "stiffness-product call (block kernel + halo pass)",
                 "algorithmic_bytes": bk, "mean_us": round(1e3 * tk_ms, 2)}
-    combined_frac = (bf + bk) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS
 
     extra = {}
     if not args.no_step:
-        # one implicit step, 100 CG iterations, tol = 0 (fixed count)
+        # one implicit step, 100 CG iterations, tol = 0 (fixed count), captured graph
         dd = d.clone()
         vv = torch.zeros_like(d)
         fem.implicit_step(dd, vv, w.dt, tol=0.0, maxit=w.maxit)   # graph capture + warm-up
         torch.cuda.synchronize()
         times = []
+        st = None
         for _ in range(3):
             dd.copy_(d)
             vv.zero_()
@@ -184,8 +200,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        X = m.X
-        ref = oracle.FEM.create(w.model, X, m.tets, w.E, w.nu, pinned=m.pinned)
+        ref = oracle.FEM.create(w.model, m.X, m.tets, w.E, w.nu, pinned=m.pinned)
         dh = mg.perturbed_state(m, 0.02, seed=10)
         uh = mg.direction(m, 11)
         reps = 0
@@ -199,8 +214,8 @@ def main():
         el = time.perf_counter() - t0
         cpu = {"value": round(reps * nt / el, 1), "unit": "tet force+Kmul evals/s", "cores": 1,
                "kind": "oracle",
-               "sample": f"{reps} force+Kmul passes over the full {nt}-tet mesh, FP64, serial C, "
-                         f"{el:.1f} s"}
+               "sample": f"{reps} force+Kmul passes over the full {nt}-tet mesh (FP64, serial C "
+                         f"oracle, 1 thread) in {el:.1f} s"}
 
     out = {
         "metric": "tet force+Kmul evals/s (1.6M tets); batched & adjoint vs plain, same GPU",
@@ -213,22 +228,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 element math, f64 vertex vectors",
+        "dtype": "f32 element math, f64 vertex vectors and accumulation",
         "data": "synthetic",
-        "config": {"workload": f"{args.n}^3 Kuhn cube, neo-Hookean, 1 force + 1 Kmul per step, cold caches",
+        "config": {"workload": f"{args.n}^3 Kuhn cube (6 tets/cell), neo-Hookean E=1e6 nu=0.45, "
+                               f"1 force + 1 Kmul per step, cold caches",
                    "tets": nt, "verts": nv, "strategy": args.strategy, "order": args.order,
                    "block": fem.get_strategy()[1],
-                   "protocol": "1 GiB cache flush before each call; HIP events on the launch stream"},
+                   "protocol": "1 GiB read-only cache flush before each call; HIP events on the launch stream"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "force_us_median": round(1e3 * med_f, 2),
-        "kmul_us_median": round(1e3 * med_k, 2),
-        "combined_hbm_frac": round(combined_frac, 4),
-        "warm_evals_per_s": round(nt / (warm_ms * 1e-3), 1),
-        "warm_force_us": round(1e3 * statistics.mean(r["wtf"]), 2),
-        "warm_kmul_us": round(1e3 * statistics.mean(r["wtk"]), 2),
+        "force_us_mean": round(1e3 * tf_ms, 2),
+        "kmul_us_mean": round(1e3 * tk_ms, 2),
+        "combined_hbm_frac": round((bf + bk) / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "warm_evals_per_s": round(nt / (r["warm_ms"] * 1e-3), 1),
+        "warm_step_us": round(1e3 * r["warm_ms"], 2),
         "timed_wall_s": round(r["wall"], 4),
         "setup_s": round(t_setup, 3),
+        "kernel_source": kernel_source_hash(),
     }
     out.update(extra)
     if others:

@@ -389,6 +389,15 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a) {
 // that list (packed: 4 x 8 bits per word when every block has <= 256 vertices,
 // else 2 x 16 bits in each of two words).
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i on XCD i mod
+// 8), each XCD with its own L2.  Give XCD x one contiguous range of tet blocks,
+// so that neighbouring (Morton-adjacent) blocks, which share vertices, run under
+// the same L2.  A bijection of [0, nblk).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk) {
+    const uint32_t q = nblk >> 3, r = nblk & 7u, x = b & 7u, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
 template <int W> __device__ __forceinline__ void unpack_slots(const ElemArgs &a, uint32_t t, uint32_t *s) {
     if (W == 1) {
         const uint32_t w = ldc<uint32_t>(a.slot[0], t);
@@ -436,9 +445,10 @@ __device__ __forceinline__ void reduce_slot(const ElemArgs &a, const uint16_t *s
         stc<double>(a.out[1], gv, a1);
         stc<double>(a.out[2], gv, a2);
     } else {
-        stc<double>(a.halo[0], (uint32_t)hp, a0);
-        stc<double>(a.halo[1], (uint32_t)hp, a1);
-        stc<double>(a.halo[2], (uint32_t)hp, a2);
+        double *hq = a.halo + 3 * (size_t)hp;
+        hq[0] = a0;
+        hq[1] = a1;
+        hq[2] = a2;
     }
 }
 
@@ -449,9 +459,10 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
     const uint32_t nt = a.nt;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x, BT = nthr * TPT;
     const uint32_t bsh = 31u - __clz(BT);   // BT is a power of two
-    const uint32_t vb = (uint32_t)a.blk_vptr[blockIdx.x];
-    const uint32_t nvb = (uint32_t)a.blk_vptr[blockIdx.x + 1] - vb;
-    const uint32_t t0 = blockIdx.x * BT;
+    const uint32_t blk = xcd_block(blockIdx.x, a.nblk);
+    const uint32_t vb = (uint32_t)a.blk_vptr[blk];
+    const uint32_t nvb = (uint32_t)a.blk_vptr[blk + 1] - vb;
+    const uint32_t t0 = blk * BT;
     // RED == 0: incidence lists + per-tet result rows (deterministic sums);
     // RED == 1: FP64 LDS atomics into one accumulator per block vertex
     uint16_t *s_list = (uint16_t *)s_dyn4;                       // 4 BT + 8 entries
@@ -565,28 +576,29 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
                 stc<double>(a.out[1], gv, v1);
                 stc<double>(a.out[2], gv, v2);
             } else {
-                stc<double>(a.halo[0], (uint32_t)hp, v0);
-                stc<double>(a.halo[1], (uint32_t)hp, v1);
-                stc<double>(a.halo[2], (uint32_t)hp, v2);
+                double *hq = a.halo + 3 * (size_t)hp;
+                hq[0] = v0;
+                hq[1] = v1;
+                hq[2] = v2;
             }
         }
     }
 }
 
-// Sum each shared vertex's halo run (its blocks' partials, in block order).
-__global__ __launch_bounds__(256) void k_halo_reduce(const double *h0, const double *h1, const double *h2,
-                                                     const int32_t *sh_vert, const int32_t *sh_ptr, uint32_t S,
-                                                     double *o0, double *o1, double *o2, int accumulate,
-                                                     const int *skip) {
+// Sum each shared vertex's halo entries (its blocks' partials, in block order).
+__global__ __launch_bounds__(256) void k_halo_reduce(const double *halo, const int32_t *sh_vert, const int32_t *sh_ptr,
+                                                     const int32_t *sh_pos, uint32_t S, double *o0, double *o1,
+                                                     double *o2, int accumulate, const int *skip) {
     if (skip && *skip) return;
     for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
         const uint32_t v = (uint32_t)sh_vert[s];
         const int32_t j0 = sh_ptr[s], j1 = sh_ptr[s + 1];
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
         for (int32_t j = j0; j < j1; ++j) {
-            a0 += ldc<double>(h0, (uint32_t)j);
-            a1 += ldc<double>(h1, (uint32_t)j);
-            a2 += ldc<double>(h2, (uint32_t)j);
+            const double *hq = halo + 3 * (size_t)sh_pos[j];
+            a0 += hq[0];
+            a1 += hq[1];
+            a2 += hq[2];
         }
         if (accumulate) {
             a0 += ldc<double>(o0, v);
@@ -710,7 +722,8 @@ static ElemArgs base_args(ebbx_fem_s *F) {
     a.blk_hpos = F->blk_hpos.as<int32_t>();
     a.slot[0] = F->blk_local.as<uint32_t>();
     a.slot[1] = F->blk_local.as<uint32_t>() + (F->blk_w == 2 ? nt : 0);
-    for (int k = 0; k < 3; ++k) a.halo[k] = F->halo.as<double>() + (size_t)k * F->halo_n;
+    a.halo = F->halo.as<double>();
+    a.nblk = (uint32_t)F->nblk;
     return a;
 }
 
@@ -755,10 +768,9 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
             else launch_model<double, EBBX_NH>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
         }
         if (F->sh_n > 0) {
-            const double *h = F->halo.as<double>();
-            const size_t hn = (size_t)F->halo_n;
-            hipLaunchKernelGGL(k_halo_reduce, dim3(grid_n(F->sh_n, 256, 1ll << 20)), dim3(256), 0, s, h, h + hn,
-                               h + 2 * hn, F->sh_vert.as<int32_t>(), F->sh_ptr.as<int32_t>(), (uint32_t)F->sh_n,
+            hipLaunchKernelGGL(k_halo_reduce, dim3(grid_n(F->sh_n, 256, 1ll << 20)), dim3(256), 0, s,
+                               (const double *)F->halo.get(), F->sh_vert.as<int32_t>(), F->sh_ptr.as<int32_t>(),
+                               F->sh_pos.as<int32_t>(), (uint32_t)F->sh_n,
                                out, out + nv, out + 2 * nv, accumulate, skip);
             HIPCHK(hipGetLastError());
         }
@@ -1018,29 +1030,37 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
             packed[(size_t)(nt + t)] = s2 | (s3 << 16);
         }
     }
-    // halo: runs per shared (or untouched) vertex, in vertex order, entries in block order
+    // halo entries are block-major (each block writes one contiguous run); every
+    // shared (or untouched) vertex lists its entries, which ascend in block order
+    std::vector<int32_t> hpos(verts.size(), -1);
+    int32_t nh = 0;
+    for (size_t p = 0; p < verts.size(); ++p)
+        if (!own[p]) hpos[p] = nh++;
     std::vector<int32_t> count((size_t)nv, 0);
     for (size_t p = 0; p < verts.size(); ++p)
         if (!own[p]) ++count[(size_t)verts[p]];
-    std::vector<int32_t> sh_vert, sh_ptr(1, 0), start((size_t)nv, -1);
+    std::vector<int32_t> sh_vert, sh_ptr(1, 0), row((size_t)nv, -1);
     for (int64_t v = 0; v < nv; ++v) {
         const bool isolated = rp[(size_t)v + 1] == rp[(size_t)v];
         if (count[(size_t)v] > 0 || isolated) {
-            start[(size_t)v] = sh_ptr.back();
+            row[(size_t)v] = (int32_t)sh_vert.size();
             sh_vert.push_back((int32_t)v);
             sh_ptr.push_back(sh_ptr.back() + count[(size_t)v]);
         }
     }
-    std::vector<int32_t> hpos(verts.size(), -1);
+    std::vector<int32_t> sh_pos((size_t)nh), fillc(sh_vert.size(), 0);
     for (size_t p = 0; p < verts.size(); ++p)
-        if (!own[p]) hpos[p] = start[(size_t)verts[p]]++;
+        if (!own[p]) {
+            const int32_t r = row[(size_t)verts[p]];
+            sh_pos[(size_t)(sh_ptr[(size_t)r] + fillc[(size_t)r]++)] = hpos[p];
+        }
     F->blk_tets = bt;
     F->nblk = nblk;
     F->blk_maxv = maxv;
     F->blk_w = w;
     F->blk_nverts = (int64_t)verts.size();
     F->sh_n = (int64_t)sh_vert.size();
-    F->halo_n = (int64_t)sh_ptr.back();
+    F->halo_n = (int64_t)nh;
     auto up = [&](DevBuf &dst, const void *src, size_t bytes) {
         dst.reset(std::max<size_t>(bytes, 8), s);
         if (bytes) HIPCHK(hipMemcpy(dst.get(), src, bytes, hipMemcpyHostToDevice));
@@ -1053,6 +1073,7 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
     up(F->blk_local, packed.data(), packed.size() * sizeof(uint32_t));
     up(F->sh_vert, sh_vert.data(), sh_vert.size() * sizeof(int32_t));
     up(F->sh_ptr, sh_ptr.data(), sh_ptr.size() * sizeof(int32_t));
+    up(F->sh_pos, sh_pos.data(), sh_pos.size() * sizeof(int32_t));
     F->halo.reset(std::max<size_t>((size_t)F->halo_n * 3 * sizeof(double), 8), s);
     F->blocks_built = true;
 }

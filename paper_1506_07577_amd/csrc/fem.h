@@ -31,7 +31,8 @@ struct ElemArgs {
     const uint16_t *blk_list;   // incidences c*BT + local tet of each block vertex, fixed order
     const int32_t *blk_hpos;    // per block vertex: halo position, or -1 if the block owns it
     const uint32_t *slot[2];    // packed corner slots within the block (one or two words per tet)
-    double *halo[3];            // partial sums of shared vertices, per component
+    double *halo;               // partial sums of shared vertices, 3 per entry, block-major
+    uint32_t nblk;              // tet blocks
     int accumulate;             // 1: out += result
     const int *skip;            // nullable device flag: nonzero = return at once (converged solve)
 };
@@ -73,7 +74,7 @@ struct ebbx_fem_s {
     int64_t blk_nverts = 0;    // entries of blk_verts over all blocks
     int64_t sh_n = 0;          // vertices summed from the halo (shared or untouched)
     int64_t halo_n = 0;        // halo entries
-    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_list, blk_hpos, blk_local, halo, sh_vert, sh_ptr;
+    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_list, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos;
     bool blocks_built = false;
 
     // implicit-step state (allocated on first step)
