@@ -265,6 +265,42 @@ typedef struct {
 ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
                                ebbx_step_stats *stats_dev, ebbx_stream stream);
 
+/* ---- adjoint (vector-Jacobian products) ---------------------------------- */
+
+/* T[a, w] = grad_x (w^T K(x) a) at displacement d: per tet the second
+ * directional derivative Q = d2P[dF_a, dF_w] (dF_a = dA B, dF_w = dW B) of
+ * the first Piola-Kirchhoff stress, scattered as -V0 Q B^T like the forces.
+ * out (+)= T[a, w]; FP64 (3, nv).  EBBX_E_PHASE if out aliases d, a or w. */
+ebbx_status ebbx_fem_Tmul(ebbx_fem fem, const double *d, const double *a, const double *w, double *out,
+                          int32_t accumulate, ebbx_stream stream);
+
+/* E_bar[t] += w_t . (dt f_t(d) + dt^2 K_t(d) v) / E_t for every tet (forces and
+ * stiffness are linear in the per-tet Young's modulus at fixed Poisson ratio).
+ * E_bar: FP64 (nt) device, accumulated.  E_t is the per-tet modulus in use (see
+ * ebbx_fem_set_material) or the uniform one. */
+ebbx_status ebbx_fem_E_grad(ebbx_fem fem, const double *d, const double *v, const double *w, double dt,
+                            double *E_bar, ebbx_stream stream);
+
+/* Replace the material: per-tet E_tet_dev (nt FP64, borrowed and kept as the
+ * E_t of ebbx_fem_E_grad) or uniform E; per-tet nu_tet_dev (nt FP64) or
+ * uniform nu.  Enqueued on stream. */
+ebbx_status ebbx_fem_set_material(ebbx_fem fem, const double *E_tet_dev, const double *nu_tet_dev, double E,
+                                  double nu, ebbx_stream stream);
+
+/* Vector-Jacobian product of one ebbx_implicit_step taken from (d_n, v_n) to
+ * (d_{n+1}, v_{n+1}).  Given gx = dL/dd_{n+1} and gv = dL/dv_{n+1}:
+ *   g^ = gv + dt gx;  solve A w = Pi g^ with the step's masked PCG
+ *   (A = M - dt^2 K(d_n), same params);
+ *   d_bar = gx + dt K w + dt^2 T[v_{n+1}, w]   (= dL/dd_n, overwritten)
+ *   v_bar = g^ + dt^2 K w                      (= dL/dv_n, overwritten)
+ *   E_bar[t] += w_t . (dt f_t + dt^2 K_t v_{n+1}) / E_t   (nullable)
+ * stats_dev (nullable) receives the adjoint solve's report.  Inputs must not
+ * alias outputs (EBBX_E_PHASE). */
+ebbx_status ebbx_implicit_step_vjp(ebbx_fem fem, const double *d_n, const double *v_np1,
+                                   const ebbx_step_params *params, const double *gx, const double *gv,
+                                   double *d_bar, double *v_bar, double *E_bar, ebbx_step_stats *stats_dev,
+                                   ebbx_stream stream);
+
 /* Copy a device stats record to the host; synchronises the stream. */
 ebbx_status ebbx_stats_fetch(const ebbx_step_stats *stats_dev, ebbx_step_stats *host,
                              ebbx_stream stream);

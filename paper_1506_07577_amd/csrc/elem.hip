@@ -227,6 +227,78 @@ __device__ __forceinline__ bool dstress_scaled(T mu, T lam, T V0, const T *G, co
     }
 }
 
+// -V0 d2P[A, W]: the derivative of dP[A] along W (symmetric in A and W)
+template <class T, int MODEL>
+__device__ __forceinline__ bool d2stress_scaled(T mu, T lam, T V0, const T *G, const T *A, const T *W, T *Q) {
+    if (MODEL == EBBX_STVK) {
+        // P = F S: d2P[A,W] = A S'[W] + W S'[A] + F S''[A,W],
+        // S'[X] = 2 mu sym(F^T X) + lam tr(F^T X) I, S''[A,W] = 2 mu sym(A^T W) + lam tr(A^T W) I
+        T FtA[9], FtW[9], AtW[9], GtA[9], GtW[9];
+        mulTN3(G, A, GtA);
+        mulTN3(G, W, GtW);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            FtA[k] = A[k] + GtA[k];
+            FtW[k] = W[k] + GtW[k];
+        }
+        mulTN3(A, W, AtW);
+        T SA[9], SW[9], S2[9];
+        const T m = -V0 * mu, l = -V0 * lam;
+        const T la = l * (FtA[0] + FtA[4] + FtA[8]), lw = l * (FtW[0] + FtW[4] + FtW[8]),
+                l2 = l * (AtW[0] + AtW[4] + AtW[8]);
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                SA[3 * i + j] = m * (FtA[3 * i + j] + FtA[3 * j + i]);
+                SW[3 * i + j] = m * (FtW[3 * i + j] + FtW[3 * j + i]);
+                S2[3 * i + j] = m * (AtW[3 * i + j] + AtW[3 * j + i]);
+            }
+        SA[0] += la; SA[4] += la; SA[8] += la;
+        SW[0] += lw; SW[4] += lw; SW[8] += lw;
+        S2[0] += l2; S2[4] += l2; S2[8] += l2;
+        T X[9], Y[9];
+        mul3(A, SW, X);
+        muladd3(X, W, SA, Y);     // A S'[W] + W S'[A]
+        muladd3(Y, G, S2, X);     // + G S''
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Q[k] = X[k] + S2[k];   // + S'' (the I of F = I + G)
+        return true;
+    } else {
+        // d/dW of  mu A + c N A^T N + lam (N:A) N,  dN[W] = -N W^T N,  dc[W] = -lam (N:W)
+        const T jm1 = jm1_of(G);
+        const T J = T(1) + jm1;
+        const T iJ = t_rcp(J);
+        const T lnJ = t_log1p(jm1);
+        T N[9];
+        cof_IpG(G, N);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) N[k] *= iJ;
+        T NAt[9], NAtN[9], NWt[9], NWtN[9], X1[9], X2[9];
+        mulNT3(N, A, NAt);
+        mul3(NAt, N, NAtN);
+        mulNT3(N, W, NWt);
+        mul3(NWt, N, NWtN);
+        mulNT3(NWtN, A, X1);   // N W^T N A^T
+        mul3(X1, N, X2);       // N W^T N A^T N
+        mulNT3(NAtN, W, X1);   // N A^T N W^T
+        T X3[9];
+        mul3(X1, N, X3);       // N A^T N W^T N
+        T NA = T(0), NW = T(0), NWNA = T(0);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            NA += N[k] * A[k];
+            NW += N[k] * W[k];
+            NWNA += NWtN[k] * A[k];
+        }
+        const T c = mu - lam * lnJ;
+        const T s1 = V0 * lam * NW, s2 = V0 * lam * NA, s3 = V0 * c, s4 = V0 * lam * NWNA;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Q[k] = s1 * NAtN[k] + s2 * NWtN[k] + s3 * (X2[k] + X3[k]) + s4 * N[k];
+        return J > T(0);
+    }
+}
+
 // The 12 diagonal entries K[(a,c),(a,c)] = -V0 dP(e_c b_a^T) : (e_c b_a^T) of one
 // tet, in closed form for a rank-one dF = e_c b^T:
 //   StVK: b^T S b + mu (|f_c|^2 |b|^2 + (f_c . b)^2) + lam (f_c . b)^2, f_c = row c of F
@@ -317,9 +389,17 @@ template <class T> __device__ __forceinline__ void corner_out(const T *Ps, const
 
 template <class T, int MODEL, int OP>
 __device__ __forceinline__ bool eval_tet(T mu, T lam, const T *b, T V0, const double (&qd)[4][3],
-                                         const double (&qu)[4][3], T *h) {
+                                         const double (&qu)[4][3], T *h, const double (*qw)[3] = nullptr) {
     T G[9];
     grad_from(qd, b, G);
+    if (OP == OP_TMUL) {
+        T FA[9], FW[9], Q[9];
+        grad_from(qu, b, FA);
+        grad_from(*(const double(*)[4][3])qw, b, FW);
+        const bool ok = d2stress_scaled<T, MODEL>(mu, lam, V0, G, FA, FW, Q);
+        corner_out(Q, b, h);
+        return ok;
+    }
     if (OP == OP_FORCE) {
         T P[9];
         const bool ok = stress_scaled<T, MODEL>(mu, lam, V0, G, P);
@@ -359,16 +439,17 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a) {
     uint32_t v[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = (uint32_t)ldc<int32_t>(a.key[c], t);
-    double qd[4][3], qu[4][3];
+    double qd[4][3], qu[4][3], qw[4][3];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             qd[c][k] = ldc<double>(a.d[k], v[c]);
-            qu[c][k] = (OP == OP_KMUL) ? ldc<double>(a.u[k], v[c]) : 0.0;
+            qu[c][k] = (OP == OP_KMUL || OP == OP_TMUL) ? ldc<double>(a.u[k], v[c]) : 0.0;
+            qw[c][k] = (OP == OP_TMUL) ? ldc<double>(a.w[k], v[c]) : 0.0;
         }
     T h[12];
-    const bool ok = eval_tet<T, MODEL, OP>(mu, lam, b, V0, qd, qu, h);
+    const bool ok = eval_tet<T, MODEL, OP>(mu, lam, b, V0, qd, qu, h, qw);
     if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv, 1ull);
     if (SC == SC_ATOMIC) {
 #pragma unroll
@@ -466,9 +547,11 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
     // RED == 0: incidence lists + per-tet result rows (deterministic sums);
     // RED == 1: FP64 LDS atomics into one accumulator per block vertex
     uint16_t *s_list = (uint16_t *)s_dyn4;                       // 4 BT + 8 entries
+    constexpr int NQ = OP == OP_TMUL ? 3 : OP == OP_KMUL ? 2 : 1;   // staged vertex fields
     double *s_d = (double *)((char *)s_dyn4 + (RED == 0 ? 8 * BT + 16 : 0));
     double *s_u = s_d + 3 * nvb;
-    T *s_h = (T *)(s_d + (OP == OP_KMUL ? 6 : 3) * nvb);
+    double *s_w = s_u + 3 * nvb;
+    T *s_h = (T *)(s_d + 3 * NQ * nvb);
     double *s_acc = (double *)s_h;
 
     // this thread's first block vertex
@@ -515,7 +598,8 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * nvb + tid] = ldc<double>(a.d[k], gv0);
-            if (OP == OP_KMUL) s_u[k * nvb + tid] = ldc<double>(a.u[k], gv0);
+            if (NQ > 1) s_u[k * nvb + tid] = ldc<double>(a.u[k], gv0);
+            if (NQ > 2) s_w[k * nvb + tid] = ldc<double>(a.w[k], gv0);
             if (RED == 1) s_acc[k * nvb + tid] = 0.0;
         }
     }
@@ -524,7 +608,8 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * nvb + i] = ldc<double>(a.d[k], gv);
-            if (OP == OP_KMUL) s_u[k * nvb + i] = ldc<double>(a.u[k], gv);
+            if (NQ > 1) s_u[k * nvb + i] = ldc<double>(a.u[k], gv);
+            if (NQ > 2) s_w[k * nvb + i] = ldc<double>(a.w[k], gv);
             if (RED == 1) s_acc[k * nvb + i] = 0.0;
         }
     }
@@ -533,16 +618,17 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
     for (int r = 0; r < TPT; ++r) {
         const uint32_t tl = r * nthr + tid, t = t0 + tl;
         if (t < nt) {
-            double qd[4][3], qu[4][3];
+            double qd[4][3], qu[4][3], qw[4][3];
 #pragma unroll
             for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
                     qd[c][k] = s_d[k * nvb + sl[r][c]];
-                    qu[c][k] = (OP == OP_KMUL) ? s_u[k * nvb + sl[r][c]] : 0.0;
+                    qu[c][k] = (NQ > 1) ? s_u[k * nvb + sl[r][c]] : 0.0;
+                    qw[c][k] = (NQ > 2) ? s_w[k * nvb + sl[r][c]] : 0.0;
                 }
             T h[12];
-            const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h);
+            const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
             if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv, 1ull);
             if (RED == 0) {
 #pragma unroll
@@ -691,10 +777,12 @@ static void launch_model(bool block, ElemOp op, int sc, int tpt, int w, int red,
     if (block) {
         if (op == OP_FORCE) launch_block<T, MODEL, OP_FORCE>(tpt, w, red, a, threads, grid, shmem, s);
         else if (op == OP_KMUL) launch_block<T, MODEL, OP_KMUL>(tpt, w, red, a, threads, grid, shmem, s);
+        else if (op == OP_TMUL) launch_block<T, MODEL, OP_TMUL>(tpt, w, red, a, threads, grid, shmem, s);
         else launch_block<T, MODEL, OP_DIAG>(tpt, w, red, a, threads, grid, shmem, s);
     } else {
         if (op == OP_FORCE) launch_flat<T, MODEL, OP_FORCE>(sc, a, threads, s);
         else if (op == OP_KMUL) launch_flat<T, MODEL, OP_KMUL>(sc, a, threads, s);
+        else if (op == OP_TMUL) launch_flat<T, MODEL, OP_TMUL>(sc, a, threads, s);
         else launch_flat<T, MODEL, OP_DIAG>(sc, a, threads, s);
     }
 }
@@ -732,13 +820,14 @@ static void set_vec(const double *(&dst)[3], const double *p, uint32_t nv) {
 }
 
 size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
-    const size_t stage = (size_t)3 * (op == OP_KMUL ? 2 : 1) * F->blk_maxv * sizeof(double);
+    const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
+    const size_t stage = (size_t)3 * nq * F->blk_maxv * sizeof(double);
     if (F->blk_red == 1) return stage + (size_t)3 * F->blk_maxv * sizeof(double);
     return (size_t)8 * F->blk_tets + 16 + stage + (size_t)12 * F->blk_tets * F->esize;
 }
 
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
-                 hipStream_t s, const int *skip) {
+                 hipStream_t s, const int *skip, const double *w) {
     const int64_t nt = F->nt, nv = F->nv;
     if (nv == 0) return;
     if (nt == 0) {
@@ -748,6 +837,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
     ElemArgs a = base_args(F);
     set_vec(a.d, d, (uint32_t)nv);
     set_vec(a.u, u, (uint32_t)nv);
+    set_vec(a.w, w, (uint32_t)nv);
     for (int k = 0; k < 3; ++k) a.out[k] = out + (size_t)k * nv;
     a.part = F->part.get();
     a.skip = skip;
@@ -873,6 +963,100 @@ void elem_energy(ebbx_fem_s *F, const double *d, double *out_dev, hipStream_t s)
     }
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, (const double *)part, (int)g, out_dev);
+    HIPCHK(hipGetLastError());
+}
+
+// ---- gradient with respect to per-tet Young's modulus ------------------------------------------
+//
+// Forces and stiffness are linear in (mu, lam), and both are proportional to
+// E at fixed nu, so d(f_t)/dE_t = f_t / E_t and d(K_t)/dE_t = K_t / E_t:
+//   E_bar[t] += w_t . (dt f_t + dt^2 K_t v) / E_t.
+template <class T, int MODEL>
+__global__ __launch_bounds__(256) void k_egrad(ElemArgs a, const double *E_tet, double E, double dt, double *E_bar) {
+    const uint32_t nt = a.nt;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    T b[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) b[k] = ldc<T>(a.B[k], t);
+    const T V0 = ldc<T>(a.V0, t);
+    T mu, lam;
+    if (a.mu_t) {
+        mu = ldc<T>(a.mu_t, t);
+        lam = ldc<T>(a.lam_t, t);
+    } else {
+        mu = (T)a.mu;
+        lam = (T)a.lam;
+    }
+    uint32_t v[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v[c] = (uint32_t)ldc<int32_t>(a.key[c], t);
+    double qd[4][3], qv[4][3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            qd[c][k] = ldc<double>(a.d[k], v[c]);
+            qv[c][k] = ldc<double>(a.u[k], v[c]);
+        }
+    T G[9], dF[9], P[9], dP[9], hf[12], hk[12];
+    grad_from(qd, b, G);
+    grad_from(qv, b, dF);
+    stress_scaled<T, MODEL>(mu, lam, V0, G, P);
+    dstress_scaled<T, MODEL>(mu, lam, V0, G, dF, dP);
+    corner_out(P, b, hf);
+    corner_out(dP, b, hk);
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            acc += ldc<double>(a.w[k], v[c]) * (dt * (double)hf[3 * c + k] + dt * dt * (double)hk[3 * c + k]);
+    const double Et = E_tet ? E_tet[t] : E;
+    E_bar[t] += acc / Et;
+}
+
+void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double dt, double *E_bar,
+                hipStream_t s) {
+    if (F->nt == 0) return;
+    ElemArgs a = base_args(F);
+    set_vec(a.d, d, (uint32_t)F->nv);
+    set_vec(a.u, v, (uint32_t)F->nv);
+    set_vec(a.w, w, (uint32_t)F->nv);
+    const unsigned g = grid_n(F->nt, 256, 1ll << 31);
+    const double *Et = F->per_tet ? F->E_tet : nullptr;
+    if (F->prec == EBBX_F32) {
+        if (F->model == EBBX_STVK) hipLaunchKernelGGL((k_egrad<float, EBBX_STVK>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
+        else hipLaunchKernelGGL((k_egrad<float, EBBX_NH>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
+    } else {
+        if (F->model == EBBX_STVK) hipLaunchKernelGGL((k_egrad<double, EBBX_STVK>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
+        else hipLaunchKernelGGL((k_egrad<double, EBBX_NH>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
+    }
+    HIPCHK(hipGetLastError());
+}
+
+template <class T>
+__global__ void k_material(const double *E_tet, const double *nu_tet, double E, double nu, int64_t nt, T *mat) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+        const double Et = E_tet ? E_tet[t] : E, nt_ = nu_tet ? nu_tet[t] : nu;
+        mat[t] = (T)(Et / (2.0 * (1.0 + nt_)));
+        mat[nt + t] = (T)(Et * nt_ / ((1.0 + nt_) * (1.0 - 2.0 * nt_)));
+    }
+}
+
+void elem_set_material(ebbx_fem_s *F, const double *E_tet, const double *nu_tet, double E, double nu, hipStream_t s) {
+    const int64_t nt = std::max<int64_t>(F->nt, 1);
+    if (!F->mat.get()) F->mat.reset((size_t)nt * 2 * F->esize, s);
+    F->per_tet = true;
+    F->E_tet = E_tet;
+    F->E = E;
+    F->nu = nu;
+    if (F->nt == 0) return;
+    const unsigned g = grid_n(F->nt, 256, 16384);
+    if (F->prec == EBBX_F32)
+        hipLaunchKernelGGL(k_material<float>, dim3(g), dim3(256), 0, s, E_tet, nu_tet, E, nu, F->nt, F->mat.as<float>());
+    else
+        hipLaunchKernelGGL(k_material<double>, dim3(g), dim3(256), 0, s, E_tet, nu_tet, E, nu, F->nt, F->mat.as<double>());
     HIPCHK(hipGetLastError());
 }
 

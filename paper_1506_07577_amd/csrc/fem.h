@@ -7,7 +7,7 @@ struct ebbx_fem_s;
 
 namespace ebbx {
 
-enum ElemOp { OP_FORCE = 0, OP_KMUL = 1, OP_DIAG = 2 };
+enum ElemOp { OP_FORCE = 0, OP_KMUL = 1, OP_DIAG = 2, OP_TMUL = 3 };
 
 // Everything an element kernel reads; plain pointers, passed by value.  Column
 // stores are passed as one base pointer per component, so that a kernel
@@ -20,7 +20,8 @@ struct ElemArgs {
     const void *mu_t, *lam_t;   // per-tet Lame parameters (element precision) or NULL
     double mu, lam;             // uniform material when mu_t == NULL
     const double *d[3];         // displacement columns
-    const double *u[3];         // direction columns (stiffness product)
+    const double *u[3];         // direction columns (stiffness product; `a` of T[a, w])
+    const double *w[3];         // second direction columns (`w` of T[a, w])
     double *out[3];             // reduce target columns
     void *part;                 // (nt, 12) per-corner partials (segmented reduction)
     unsigned long long *n_inv;  // inverted-element counter
@@ -41,7 +42,12 @@ struct ElemArgs {
 // out (3, nv) (+= if accumulate).  For OP_DIAG, u is ignored and out receives
 // the raw stiffness diagonal K[(v,c),(v,c)].
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
-                 hipStream_t s, const int *skip = nullptr);
+                 hipStream_t s, const int *skip = nullptr, const double *w = nullptr);
+// E_bar[t] += w_t . (dt f_t + dt^2 K_t v) / E_t over the tets (no scatter).
+void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double dt, double *E_bar,
+                hipStream_t s);
+// Recompute the per-tet Lame parameters from per-tet (or uniform) E and nu.
+void elem_set_material(ebbx_fem_s *F, const double *E_tet, const double *nu_tet, double E, double nu, hipStream_t s);
 // Total energy into out_dev[0].
 void elem_energy(ebbx_fem_s *F, const double *d, double *out_dev, hipStream_t s);
 // Rest-shape precompute; returns the number of degenerate tets.
@@ -62,6 +68,7 @@ struct ebbx_fem_s {
     int32_t model = EBBX_STVK, prec = EBBX_F64, strategy = EBBX_STRAT_ATOMIC, block = 256;
     double rho = 1000.0, E = 1e5, nu = 0.3, mu = 0.0, lam = 0.0;
     bool per_tet = false;
+    const double *E_tet = nullptr;   // borrowed per-tet Young's modulus (nullable)
     size_t esize = 8;   // bytes of one element-precision value
 
     ebbx::DevBuf B, V0, mat, mass, pinned, part, status, scratch;

@@ -65,8 +65,10 @@ __global__ void k_step_begin(CGState *st, unsigned long long *n_inv) {
 
 // b = dt (f + M g + dt K v); diag = M - dt^2 Kdiag (1 on pinned rows); r = Pi b;
 // z = D^-1 r; p = z; x = 0; partials (r.z, r.r)
+// mode 0 (step): b = dt (f + M g + dt y), with f = f(d_n) and y = K(d_n) v_n;
+// mode 1 (adjoint solve): b = f, the right-hand side placed in f beforehand.
 __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
-                                                 double dt, double gx, double gy, double gz, int precond,
+                                                 double dt, double gx, double gy, double gz, int precond, int mode,
                                                  double *part) {
     __shared__ double s4[4];
     double rz = 0.0, rr = 0.0;
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, 
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
-            const double b = dt * (w.f[i] + m * g[k] + dt * w.y[i]);
+            const double b = mode ? w.f[i] : dt * (w.f[i] + m * g[k] + dt * w.y[i]);
             const double dg = pin ? 1.0 : (precond ? m - dt * dt * w.diag[i] : 1.0);
             const double r = pin ? 0.0 : b;
             const double z = r / dg;
@@ -242,6 +244,33 @@ __global__ void k_step_end(StepVec w, int64_t n, double dt, double tol, const CG
     }
 }
 
+// adjoint: d_n copied in, g^ = gv + dt gx into f (the solve's right-hand side)
+__global__ void k_vjp_prep(const double *d, const double *gx, const double *gv, double dt, StepVec w, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        w.dn[i] = d[i];
+        w.f[i] = gv[i] + dt * gx[i];
+    }
+}
+
+// adjoint: d_bar = gx + dt K w + dt^2 T[v', w];  v_bar = g^ + dt^2 K w
+// (K w in y, T[v', w] in q, g^ in f); stats out
+__global__ void k_vjp_end(StepVec w, const double *gx, double dt, int64_t n, double *d_bar, double *v_bar,
+                          const CGState *st, double tol, ebbx_step_stats *stats) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double kw = w.y[i];
+        d_bar[i] = gx[i] + dt * kw + dt * dt * w.q[i];
+        v_bar[i] = w.f[i] + dt * dt * kw;
+    }
+    if (stats && blockIdx.x == 0 && threadIdx.x == 0) {
+        int status = st->status;
+        if (status == EBBX_OK && !st->converged && tol > 0.0) status = EBBX_E_NOT_CONVERGED;
+        stats->iters = st->iters;
+        stats->status = status;
+        stats->rel_res = st->bnorm > 0.0 ? sqrt(st->rr) / st->bnorm : 0.0;
+        stats->n_inverted = (int64_t)st->n_inv;
+    }
+}
+
 }  // namespace ebbx
 
 using namespace ebbx;
@@ -250,20 +279,29 @@ struct ebbx_fem_s::Step {
     DevBuf vec, part, state;
     StepVec w{};
     int npb = 1;
-    // graphs
-    hipGraphExec_t pre = nullptr, chunk = nullptr;
-    hipGraph_t g_pre = nullptr, g_chunk = nullptr;
+    // graphs: preambles of the step (0) and of the adjoint solve (1), and a chunk of CG iterations
+    hipGraphExec_t pre[2] = {nullptr, nullptr}, chunk = nullptr;
+    hipGraph_t g_pre[2] = {nullptr, nullptr}, g_chunk = nullptr;
     hipStream_t cap = nullptr;
     int chunk_iters = 0;
     // parameters baked into the graphs
     double dt = -1, g[3] = {0, 0, 0}, tol = -1;
     int maxit = -1, precond = -1, strategy = -1, block = -1;
     int *h_done = nullptr;   // pinned host flag for convergence checks
-    ~Step() {
-        if (pre) (void)hipGraphExecDestroy(pre);
+    void drop_graphs() {
+        for (int k = 0; k < 2; ++k) {
+            if (pre[k]) (void)hipGraphExecDestroy(pre[k]);
+            if (g_pre[k]) (void)hipGraphDestroy(g_pre[k]);
+            pre[k] = nullptr;
+            g_pre[k] = nullptr;
+        }
         if (chunk) (void)hipGraphExecDestroy(chunk);
-        if (g_pre) (void)hipGraphDestroy(g_pre);
         if (g_chunk) (void)hipGraphDestroy(g_chunk);
+        chunk = nullptr;
+        g_chunk = nullptr;
+    }
+    ~Step() {
+        drop_graphs();
         if (cap) (void)hipStreamDestroy(cap);
         if (h_done) (void)hipHostFree(h_done);
     }
@@ -353,6 +391,7 @@ ebbx_status ebbx_fem_create(ebbx_relation tets, const char *keyfield, ebbx_relat
     F->mu = params->E / (2.0 * (1.0 + params->nu));
     F->lam = params->E * params->nu / ((1.0 + params->nu) * (1.0 - 2.0 * params->nu));
     F->per_tet = E_tet != nullptr;
+    F->E_tet = E_tet;
     F->group = build_group(tr, keyfield, s);
     const int64_t nt = std::max<int64_t>(F->nt, 1), nv = std::max<int64_t>(F->nv, 1);
     F->B.reset((size_t)nt * 9 * F->esize, s);
@@ -491,44 +530,50 @@ hipGraphExec_t capture_end(hipStream_t cap, hipGraph_t *g) {
     return ex;
 }
 
-void build_step_graphs(ebbx_fem_s *F, const ebbx_step_params &p) {
+// Capture the preamble of `mode` (0: step, 1: adjoint solve) and, if the
+// parameters changed, the CG chunk shared by both.
+void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     auto &S = *F->step;
-    if (S.pre) { (void)hipGraphExecDestroy(S.pre); S.pre = nullptr; }
-    if (S.chunk) { (void)hipGraphExecDestroy(S.chunk); S.chunk = nullptr; }
-    if (S.g_pre) { (void)hipGraphDestroy(S.g_pre); S.g_pre = nullptr; }
-    if (S.g_chunk) { (void)hipGraphDestroy(S.g_chunk); S.g_chunk = nullptr; }
+    const bool same = S.dt == p.dt && !std::memcmp(S.g, p.g, sizeof S.g) && S.tol == p.tol && S.maxit == p.maxit &&
+                      S.precond == p.precond && S.strategy == F->strategy && S.block == F->block && S.chunk;
+    if (!same) S.drop_graphs();
+    if (S.pre[mode] && S.chunk) return;
     const int64_t nv = F->nv;
     const int npb = S.npb;
     CGState *st = S.state.as<CGState>();
     double *part = S.part.as<double>();
     unsigned long long *n_inv = F->status.as<unsigned long long>();
     hipStream_t cs = S.cap;
-    // preamble: forces, K v, Jacobi diagonal, rhs, initial residual
+    // preamble: (step) forces and K v; Jacobi diagonal; rhs; initial residual
     capture_begin(cs);
     hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(64), 0, cs, st, n_inv);
-    elem_launch(F, OP_FORCE, S.w.dn, nullptr, S.w.f, 0, cs);
-    elem_launch(F, OP_KMUL, S.w.dn, S.w.vn, S.w.y, 0, cs);
+    if (mode == 0) {
+        elem_launch(F, OP_FORCE, S.w.dn, nullptr, S.w.f, 0, cs);
+        elem_launch(F, OP_KMUL, S.w.dn, S.w.vn, S.w.y, 0, cs);
+    }
     if (p.precond == EBBX_PRECOND_JACOBI) elem_launch(F, OP_DIAG, S.w.dn, nullptr, S.w.diag, 0, cs);
     hipLaunchKernelGGL(k_step_rhs, dim3(npb), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(), nv,
-                       p.dt, p.g[0], p.g[1], p.g[2], p.precond, part);
+                       p.dt, p.g[0], p.g[1], p.g[2], p.precond, mode, part);
     hipLaunchKernelGGL(k_step_init, dim3(1), dim3(VT), 0, cs, st, (const double *)part, npb,
                        (const unsigned long long *)n_inv);
     HIPCHK(hipGetLastError());
-    S.pre = capture_end(cs, &S.g_pre);
-    // a chunk of CG iterations, each kernel predicated on the device flag st->done
-    S.chunk_iters = std::max(1, std::min(p.maxit, 128));
-    capture_begin(cs);
-    for (int it = 0; it < S.chunk_iters; ++it) {
-        elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &st->done);
-        hipLaunchKernelGGL(k_cg_Ap, dim3(npb), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(), nv,
-                           p.dt, (const CGState *)st, part);
-        hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(VT), 0, cs, st, (const double *)part, npb);
-        hipLaunchKernelGGL(k_cg_update, dim3(npb), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, part);
-        hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(VT), 0, cs, st, (const double *)part, npb, p.tol, p.maxit);
-        hipLaunchKernelGGL(k_cg_p, dim3(npb), dim3(VT), 0, cs, S.w, nv, (const CGState *)st);
+    S.pre[mode] = capture_end(cs, &S.g_pre[mode]);
+    if (!S.chunk) {
+        // a chunk of CG iterations, each kernel predicated on the device flag st->done
+        S.chunk_iters = std::max(1, std::min(p.maxit, 128));
+        capture_begin(cs);
+        for (int it = 0; it < S.chunk_iters; ++it) {
+            elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &st->done);
+            hipLaunchKernelGGL(k_cg_Ap, dim3(npb), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
+                               nv, p.dt, (const CGState *)st, part);
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(VT), 0, cs, st, (const double *)part, npb);
+            hipLaunchKernelGGL(k_cg_update, dim3(npb), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, part);
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(VT), 0, cs, st, (const double *)part, npb, p.tol, p.maxit);
+            hipLaunchKernelGGL(k_cg_p, dim3(npb), dim3(VT), 0, cs, S.w, nv, (const CGState *)st);
+        }
+        HIPCHK(hipGetLastError());
+        S.chunk = capture_end(cs, &S.g_chunk);
     }
-    HIPCHK(hipGetLastError());
-    S.chunk = capture_end(cs, &S.g_chunk);
     S.dt = p.dt;
     std::memcpy(S.g, p.g, sizeof S.g);
     S.tol = p.tol;
@@ -538,47 +583,38 @@ void build_step_graphs(ebbx_fem_s *F, const ebbx_step_params &p) {
     S.block = F->block;
 }
 
-}  // namespace
-
-extern "C" ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
-                                          ebbx_step_stats *stats_dev, ebbx_stream stream) {
-    EBBX_API_BEGIN
-    auto *F = check_fem(fem);
+void check_step_params(const ebbx_step_params *params) {
     if (!params) fail(EBBX_E_ARG, "params is NULL");
     const ebbx_step_params &p = *params;
     if (!(p.dt > 0.0)) fail(EBBX_E_ARG, "dt must be > 0");
     if (p.maxit < 0) fail(EBBX_E_ARG, "maxit must be >= 0");
     if (!(p.tol >= 0.0)) fail(EBBX_E_ARG, "tol must be >= 0");
     if (p.precond != EBBX_PRECOND_NONE && p.precond != EBBX_PRECOND_JACOBI) fail(EBBX_E_ARG, "bad precond");
+}
+
+void ensure_step(ebbx_fem_s *F, hipStream_t s) {
+    if (F->step) return;
     const int64_t nv = F->nv;
-    if (nv > 0 && (!d || !v)) fail(EBBX_E_ARG, "d or v is NULL");
-    if (nv > 0 && overlap(d, v, (size_t)(3 * nv) * sizeof(double))) fail(EBBX_E_PHASE, "d aliases v");
-    hipStream_t s = (hipStream_t)stream;
-    if (!F->step) {
-        auto S = std::make_unique<ebbx_fem_s::Step>();
-        const int64_t n3 = 3 * std::max<int64_t>(nv, 1);
-        S->vec.reset((size_t)n3 * 10 * sizeof(double), s);
-        double *b = S->vec.as<double>();
-        S->w = StepVec{b, b + n3, b + 2 * n3, b + 3 * n3, b + 4 * n3, b + 5 * n3, b + 6 * n3, b + 7 * n3, b + 8 * n3,
-                       b + 9 * n3};
-        S->npb = npb_for(nv);
-        S->part.reset((size_t)S->npb * 2 * sizeof(double), s);
-        S->state.reset(sizeof(CGState), s);
-        HIPCHK(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
-        HIPCHK(hipHostMalloc((void **)&S->h_done, sizeof(int), hipHostMallocDefault));
-        HIPCHK(hipStreamSynchronize(s));
-        F->step = std::move(S);
-    }
+    auto S = std::make_unique<ebbx_fem_s::Step>();
+    const int64_t n3 = 3 * std::max<int64_t>(nv, 1);
+    S->vec.reset((size_t)n3 * 10 * sizeof(double), s);
+    double *b = S->vec.as<double>();
+    S->w = StepVec{b, b + n3, b + 2 * n3, b + 3 * n3, b + 4 * n3, b + 5 * n3, b + 6 * n3, b + 7 * n3, b + 8 * n3,
+                   b + 9 * n3};
+    S->npb = npb_for(nv);
+    S->part.reset((size_t)S->npb * 2 * sizeof(double), s);
+    S->state.reset(sizeof(CGState), s);
+    HIPCHK(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
+    HIPCHK(hipHostMalloc((void **)&S->h_done, sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipStreamSynchronize(s));
+    F->step = std::move(S);
+}
+
+// Launch the preamble of `mode` and the CG chunks on s.
+void run_solve(ebbx_fem_s *F, const ebbx_step_params &p, int mode, hipStream_t s) {
+    build_graphs(F, p, mode);
     auto &S = *F->step;
-    if (S.dt != p.dt || std::memcmp(S.g, p.g, sizeof S.g) || S.tol != p.tol || S.maxit != p.maxit ||
-        S.precond != p.precond || S.strategy != F->strategy || S.block != F->block || !S.pre)
-        build_step_graphs(F, p);
-    if (nv > 0) {
-        hipLaunchKernelGGL(k_copy_in, dim3(npb_for(3 * nv)), dim3(VT), 0, s, (const double *)d, (const double *)v,
-                           S.w.dn, S.w.vn, 3 * nv);
-        HIPCHK(hipGetLastError());
-    }
-    HIPCHK(hipGraphLaunch(S.pre, s));
+    HIPCHK(hipGraphLaunch(S.pre[mode], s));
     const int nchunks = p.maxit > 0 ? (p.maxit + S.chunk_iters - 1) / S.chunk_iters : 0;
     CGState *st = S.state.as<CGState>();
     for (int c = 0; c < nchunks; ++c) {
@@ -590,9 +626,102 @@ extern "C" ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, co
             if (*S.h_done) break;
         }
     }
+}
+
+}  // namespace
+
+extern "C" ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
+                                          ebbx_step_stats *stats_dev, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    check_step_params(params);
+    const ebbx_step_params &p = *params;
+    const int64_t nv = F->nv;
+    if (nv > 0 && (!d || !v)) fail(EBBX_E_ARG, "d or v is NULL");
+    if (nv > 0 && overlap(d, v, (size_t)(3 * nv) * sizeof(double))) fail(EBBX_E_PHASE, "d aliases v");
+    hipStream_t s = (hipStream_t)stream;
+    ensure_step(F, s);
+    auto &S = *F->step;
+    if (nv > 0) {
+        hipLaunchKernelGGL(k_copy_in, dim3(npb_for(3 * nv)), dim3(VT), 0, s, (const double *)d, (const double *)v,
+                           S.w.dn, S.w.vn, 3 * nv);
+        HIPCHK(hipGetLastError());
+    }
+    run_solve(F, p, 0, s);
     hipLaunchKernelGGL(k_step_end, dim3(npb_for(3 * std::max<int64_t>(nv, 1))), dim3(VT), 0, s, S.w, 3 * nv, p.dt,
-                       p.tol, (const CGState *)st, d, v, stats_dev);
+                       p.tol, (const CGState *)S.state.as<CGState>(), d, v, stats_dev);
     HIPCHK(hipGetLastError());
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_implicit_step_vjp(ebbx_fem fem, const double *d_n, const double *v_np1,
+                                              const ebbx_step_params *params, const double *gx, const double *gv,
+                                              double *d_bar, double *v_bar, double *E_bar,
+                                              ebbx_step_stats *stats_dev, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    check_step_params(params);
+    const ebbx_step_params &p = *params;
+    const int64_t nv = F->nv;
+    if (nv > 0 && (!d_n || !v_np1 || !gx || !gv || !d_bar || !v_bar)) fail(EBBX_E_ARG, "a vector argument is NULL");
+    const size_t bytes = (size_t)(3 * nv) * sizeof(double);
+    if (nv > 0) {
+        const void *ins[4] = {d_n, v_np1, gx, gv};
+        for (const void *o : {(const void *)d_bar, (const void *)v_bar})
+            for (const void *i : ins)
+                if (overlap(o, i, bytes)) fail(EBBX_E_PHASE, "an output of the adjoint aliases an input");
+        if (overlap(d_bar, v_bar, bytes)) fail(EBBX_E_PHASE, "d_bar aliases v_bar");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ensure_step(F, s);
+    auto &S = *F->step;
+    if (nv > 0) {
+        hipLaunchKernelGGL(k_vjp_prep, dim3(npb_for(3 * nv)), dim3(VT), 0, s, d_n, gx, gv, p.dt, S.w, 3 * nv);
+        HIPCHK(hipGetLastError());
+    }
+    // A w = Pi (gv + dt gx), with A = M - dt^2 K(d_n); w ends in x
+    run_solve(F, p, 1, s);
+    elem_launch(F, OP_KMUL, S.w.dn, S.w.x, S.w.y, 0, s);
+    elem_launch(F, OP_TMUL, S.w.dn, v_np1, S.w.q, 0, s, nullptr, S.w.x);
+    hipLaunchKernelGGL(k_vjp_end, dim3(npb_for(3 * std::max<int64_t>(nv, 1))), dim3(VT), 0, s, S.w, gx, p.dt, 3 * nv,
+                       d_bar, v_bar, (const CGState *)S.state.as<CGState>(), p.tol, stats_dev);
+    HIPCHK(hipGetLastError());
+    if (E_bar) elem_egrad(F, S.w.dn, v_np1, S.w.x, p.dt, E_bar, s);
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_fem_Tmul(ebbx_fem fem, const double *d, const double *a, const double *w, double *out,
+                                     int32_t accumulate, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    if ((!d || !a || !w || !out) && F->nv > 0) fail(EBBX_E_ARG, "a vector argument is NULL");
+    const size_t bytes = (size_t)(3 * F->nv) * sizeof(double);
+    if (F->nv > 0 && (overlap(out, d, bytes) || overlap(out, a, bytes) || overlap(out, w, bytes)))
+        fail(EBBX_E_PHASE, "out aliases an input");
+    elem_launch(F, OP_TMUL, d, a, out, accumulate ? 1 : 0, (hipStream_t)stream, nullptr, w);
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_fem_E_grad(ebbx_fem fem, const double *d, const double *v, const double *w, double dt,
+                                       double *E_bar, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    if ((!d || !v || !w) && F->nv > 0) fail(EBBX_E_ARG, "a vector argument is NULL");
+    if (!E_bar && F->nt > 0) fail(EBBX_E_ARG, "E_bar is NULL");
+    elem_egrad(F, d, v, w, dt, E_bar, (hipStream_t)stream);
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_fem_set_material(ebbx_fem fem, const double *E_tet, const double *nu_tet, double E,
+                                             double nu, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    if (!E_tet && !(E > 0.0)) fail(EBBX_E_ARG, "E must be > 0");
+    if (!nu_tet && !(nu > -1.0 && nu < 0.5)) fail(EBBX_E_ARG, "nu must be in (-1, 0.5)");
+    const bool had = F->per_tet;
+    elem_set_material(F, E_tet, nu_tet, E, nu, (hipStream_t)stream);
+    // captured solver graphs read the material arrays only if they existed then
+    if (!had && F->step) F->step->drop_graphs();
     EBBX_API_END
 }
 

@@ -103,6 +103,10 @@ def lib():
         "ebbx_implicit_step": ([P, P, P, C.POINTER(StepParams), P, P], I32_),
         "ebbx_stats_fetch": ([P, C.POINTER(StepStats), P], I32_),
         "ebbx_cache_flush": ([C.c_size_t, P], I32_),
+        "ebbx_fem_Tmul": ([P, P, P, P, P, I32_, P], I32_),
+        "ebbx_fem_E_grad": ([P, P, P, P, D, P, P], I32_),
+        "ebbx_fem_set_material": ([P, P, P, D, D, P], I32_),
+        "ebbx_implicit_step_vjp": ([P, P, P, C.POINTER(StepParams), P, P, P, P, P, P, P], I32_),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -227,6 +231,7 @@ class Fem:
         self.tets, self.verts = tets, verts
         self.nt, self.nv = tets.size, verts.size
         self.model, self.elem_prec = model, elem_prec
+        self.E, self.nu = float(E), float(nu)
 
     def close(self):
         if self.h:
@@ -292,6 +297,51 @@ class Fem:
         n = C.c_int64()
         _check(lib().ebbx_fem_status(self.h, C.byref(n), int(bool(reset)), _stream(stream)))
         return n.value
+
+    def tmul(self, d, a, w, out=None, accumulate=False, stream=None):
+        for t, n in ((d, "d"), (a, "a"), (w, "w")):
+            self._vec(t, n)
+        if out is None:
+            out = torch.empty_like(d)
+        self._vec(out, "out")
+        _check(lib().ebbx_fem_Tmul(self.h, _ptr(d), _ptr(a), _ptr(w), _ptr(out), int(bool(accumulate)),
+                                   _stream(stream)))
+        return out
+
+    def E_grad(self, d, v, w, dt, E_bar, stream=None):
+        for t, n in ((d, "d"), (v, "v"), (w, "w")):
+            self._vec(t, n)
+        _dev(E_bar, torch.float64, "E_bar")
+        _check(lib().ebbx_fem_E_grad(self.h, _ptr(d), _ptr(v), _ptr(w), float(dt), _ptr(E_bar),
+                                     _stream(stream)))
+        return E_bar
+
+    def set_material(self, E_tet=None, nu_tet=None, E=0.0, nu=0.3, stream=None):
+        """Per-tet (nt,) FP64 CUDA tensors or uniform values.  The tensors are borrowed."""
+        if E_tet is not None:
+            _dev(E_tet, torch.float64, "E_tet")
+        if nu_tet is not None:
+            _dev(nu_tet, torch.float64, "nu_tet")
+        self._material = (E_tet, nu_tet)
+        _check(lib().ebbx_fem_set_material(self.h, _ptr(E_tet), _ptr(nu_tet), float(E), float(nu),
+                                           _stream(stream)))
+
+    def step_vjp(self, d_n, v_np1, gx, gv, dt, tol=1e-10, maxit=1000, precond=PRECOND_JACOBI,
+                 E_bar=None, g=(0.0, 0.0, -9.81), stats=None, stream=None):
+        """Returns (d_bar, v_bar, stats); accumulates dL/dE into E_bar if given."""
+        for t, n in ((d_n, "d_n"), (v_np1, "v_np1"), (gx, "gx"), (gv, "gv")):
+            self._vec(t, n)
+        d_bar = torch.empty_like(d_n)
+        v_bar = torch.empty_like(d_n)
+        if stats is None:
+            stats = torch.zeros(3, dtype=torch.int64, device=d_n.device)
+        if E_bar is not None:
+            _dev(E_bar, torch.float64, "E_bar")
+        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond))
+        _check(lib().ebbx_implicit_step_vjp(self.h, _ptr(d_n), _ptr(v_np1), C.byref(p), _ptr(gx), _ptr(gv),
+                                            _ptr(d_bar), _ptr(v_bar), _ptr(E_bar), _ptr(stats),
+                                            _stream(stream)))
+        return d_bar, v_bar, stats
 
     def implicit_step(self, d, v, dt, g=(0.0, 0.0, -9.81), tol=0.0, maxit=100,
                       precond=PRECOND_JACOBI, stats=None, stream=None):

@@ -1,0 +1,321 @@
+"""GPU adjoint (T-product, E-gradient, step VJP, checkpointed trajectory
+gradient) through the C-ABI against the FP64 oracle and central finite
+differences.
+
+Tolerances (normwise, ||a - b||_inf / ||b||_inf):
+  single evaluations (T-product, E-gradient), FP64: 1e-10; FP32 elements: 1e-5;
+  outputs of PCG solves run to tol 1e-13 on both sides: 1e-9 (the two solves
+  differ only in summation order, so they agree to about tol * cond(A));
+  central differences with a relative step of 1e-3: 1e-4 (truncation O(h^2)
+  plus the solver tolerance).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1506_07577_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1506_07577_amd import adjoint, ebbx
+else:  # collected on a CPU host only to be deselected
+    ebbx = adjoint = None
+
+
+def nerr(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _strat(name):
+    return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
+            "block_lds": ebbx.STRAT_BLOCK_LDS}[name]
+
+
+def _pair(m, model, E_tet, nu=0.3, prec="f64", strategy="block"):
+    """GPU FemMesh and oracle FEM over the same mesh and per-tet material."""
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=model, elem_prec=ebbx.F64 if prec == "f64" else ebbx.F32,
+                        E=float(np.median(E_tet)), nu=nu, E_tet=E_tet, strategy=_strat(strategy))
+    ref = oracle.FEM.create(model, m.X, m.tets, E_tet, nu, pinned=m.pinned)
+    return mesh, ref
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a.T), dtype=torch.float64).cuda()
+
+
+def _host(t):
+    return t.t().cpu().numpy()
+
+
+MODELS = [("stvk", oracle.STVK), ("nh", oracle.NH)]
+
+
+# ---------------------------------------------------------------------------
+# single evaluations
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strategy", ["atomic", "seg", "block", "block_lds"])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("mname,model", MODELS)
+def test_tmul_parity(mname, model, prec, strategy):
+    m = mg.jitter(mg.kuhn_cube(8), 0.01, seed=0)
+    E_tet, _, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, ref = _pair(m, model, E_tet, prec=prec, strategy=strategy)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    a = mg.direction(m, 11)
+    w = mg.direction(m, 12)
+    exp = ref.tmul(d, a, w)
+    got = _host(mesh.fem.tmul(_dev(d), _dev(a), _dev(w)))
+    tol = 1e-10 if prec == "f64" else 1e-5
+    assert nerr(got, exp) < tol
+    # accumulate mode adds onto what is there
+    out = _dev(np.ones_like(d))
+    mesh.fem.tmul(_dev(d), _dev(a), _dev(w), out=out, accumulate=True)
+    assert nerr(_host(out) - 1.0, exp) < tol
+
+
+@pytest.mark.parametrize("mname,model", MODELS)
+def test_tmul_symmetric_in_directions(mname, model):
+    # T[a, w] = grad(w^T K a) and K is symmetric, so T[a, w] = T[w, a]; the block kernel
+    # evaluates Q from the two directions in fixed roles, so this is a real check
+    m = mg.jitter(mg.kuhn_cube(5), 0.01, seed=0)
+    E_tet, _, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, _ = _pair(m, model, E_tet)
+    d = _dev(mg.perturbed_state(m, 0.02, seed=10))
+    a, w = _dev(mg.direction(m, 11)), _dev(mg.direction(m, 12))
+    t1 = _host(mesh.fem.tmul(d, a, w))
+    t2 = _host(mesh.fem.tmul(d, w, a))
+    assert nerr(t1, t2) < 1e-12
+
+
+def test_tmul_is_derivative_of_kmul():
+    # T[a, w] = grad_d (w . K(d) a): compare against central differences of the GPU Kmul
+    m = mg.jitter(mg.kuhn_cube(3), 0.01, seed=0)
+    E_tet, _, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, _ = _pair(m, oracle.NH, E_tet)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    a, w = mg.direction(m, 11), mg.direction(m, 12)
+    T = _host(mesh.fem.tmul(_dev(d), _dev(a), _dev(w)))
+    rng = np.random.default_rng(5)
+    u = rng.uniform(-1, 1, d.shape)
+    eps = 1e-6 / 3
+    kp = _host(mesh.fem.kmul(_dev(d + eps * u), _dev(a)))
+    km = _host(mesh.fem.kmul(_dev(d - eps * u), _dev(a)))
+    fd = float(np.sum(w * (kp - km)) / (2 * eps))
+    assert abs(fd - float(np.sum(T * u))) <= 1e-6 * abs(fd)
+
+
+@pytest.mark.parametrize("mname,model", MODELS)
+def test_E_grad_per_tet(mname, model):
+    # per tet t: E_bar_t = w . (dt f_t(d) + dt^2 K_t(d) v) / E_t, with f_t, K_t from a one-tet oracle FEM
+    m = mg.jitter(mg.kuhn_cube(2), 0.01, seed=0)
+    E_tet, _, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, _ = _pair(m, model, E_tet)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    v = 0.3 * mg.direction(m, 11)
+    w = mg.direction(m, 12)
+    dt = 1e-3
+    exp = np.zeros(m.nt)
+    for t in range(m.nt):
+        one = oracle.FEM.create(model, m.X, m.tets[t:t + 1], E_tet[t], 0.3)
+        exp[t] = np.sum(w * (dt * one.forces(d) + dt * dt * one.kmul(d, v))) / E_tet[t]
+    E_bar = torch.full((m.nt,), 0.5, dtype=torch.float64, device="cuda")
+    mesh.fem.E_grad(_dev(d), _dev(v), _dev(w), dt, E_bar)
+    assert nerr(E_bar.cpu().numpy() - 0.5, exp) < 1e-10
+
+
+def test_set_material_matches_bound_field():
+    m = mg.jitter(mg.kuhn_cube(4), 0.01, seed=0)
+    E_tet, _, _ = mg.adjoint_recipe(m, seed=2)
+    d = _dev(mg.perturbed_state(m, 0.02, seed=10))
+    bound = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.NH, elem_prec=ebbx.F64, E=1e5, nu=0.3, E_tet=E_tet,
+                         strategy=ebbx.STRAT_BLOCK)
+    late = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.NH, elem_prec=ebbx.F64, E=1e5, nu=0.3,
+                        strategy=ebbx.STRAT_BLOCK)
+    vv = torch.zeros_like(d)
+    late.fem.implicit_step(d.clone(), vv, 1e-3, tol=1e-8, maxit=50)   # captures graphs with the uniform material
+    Et = torch.as_tensor(E_tet, dtype=torch.float64).cuda()
+    late.fem.set_material(E_tet=Et, nu=0.3)
+    assert torch.equal(bound.fem.forces(d), late.fem.forces(d))
+    # the step after the material change uses it too (graphs are rebuilt)
+    d1, v1 = d.clone(), torch.zeros_like(d)
+    d2, v2 = d.clone(), torch.zeros_like(d)
+    bound.fem.implicit_step(d1, v1, 1e-3, tol=1e-10, maxit=200)
+    late.fem.implicit_step(d2, v2, 1e-3, tol=1e-10, maxit=200)
+    assert torch.equal(v1, v2)
+    # per-tet nu: uniform values through the per-tet path equal the uniform material
+    nu_t = torch.full((m.nt,), 0.3, dtype=torch.float64, device="cuda")
+    late.fem.set_material(E_tet=Et, nu_tet=nu_t)
+    assert torch.equal(bound.fem.forces(d), late.fem.forces(d))
+    with pytest.raises(ebbx.EbbxError):
+        late.fem.set_material(E_tet=None, nu_tet=None, E=-1.0, nu=0.3)
+
+
+# ---------------------------------------------------------------------------
+# one step's vector-Jacobian product
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strategy", ["atomic", "block"])
+@pytest.mark.parametrize("mname,model", MODELS)
+def test_step_vjp_parity(mname, model, strategy):
+    m = mg.jitter(mg.kuhn_cube(6), 0.01, seed=0)
+    E_tet, _, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, ref = _pair(m, model, E_tet, strategy=strategy)
+    d_n = mg.perturbed_state(m, 0.002, seed=10)
+    v_np1 = 0.05 * mg.direction(m, 11)
+    rng = np.random.default_rng(7)
+    gx = rng.standard_normal((m.nv, 3))
+    gv = rng.standard_normal((m.nv, 3))
+    dt = 1e-3
+    db_e, vb_e, Eb_e, st_e = ref.step_vjp(d_n, v_np1, gx, gv, dt, tol=1e-13, maxit=2000)
+    E_bar = torch.zeros(m.nt, dtype=torch.float64, device="cuda")
+    db, vb, st = mesh.fem.step_vjp(_dev(d_n), _dev(v_np1), _dev(gx), _dev(gv), dt, tol=1e-13, maxit=2000,
+                                   E_bar=E_bar)
+    s = ebbx.stats_fetch(st)
+    assert s.status == ebbx.OK and s.rel_res <= 1e-13
+    assert abs(s.iters - st_e.iters) <= 2
+    assert nerr(_host(db), db_e) < 1e-9
+    assert nerr(_host(vb), vb_e) < 1e-9
+    assert nerr(E_bar.cpu().numpy(), Eb_e) < 1e-9
+
+
+def test_step_vjp_errors_and_aliasing():
+    m = mg.kuhn_cube(3)
+    E_tet = np.full(m.nt, 1e5)
+    mesh, _ = _pair(m, oracle.NH, E_tet)
+    z = torch.zeros(3, m.nv, dtype=torch.float64, device="cuda")
+    fem = mesh.fem
+    # zero cotangent: zero gradients, zero iterations
+    db, vb, st = fem.step_vjp(z, z, z, z, 1e-3)
+    assert float(db.abs().max()) == 0.0 and float(vb.abs().max()) == 0.0
+    assert ebbx.stats_fetch(st).iters == 0
+    with pytest.raises(ebbx.EbbxError) as e:
+        fem.step_vjp(z, z, z, z, -1.0)
+    assert e.value.code == ebbx.E_ARG
+    # Tmul output aliasing an input is a phase error
+    with pytest.raises(ebbx.EbbxError) as e:
+        fem.tmul(z, z, z, out=z)
+    assert e.value.code == ebbx.E_PHASE
+
+
+# ---------------------------------------------------------------------------
+# checkpointed trajectory gradient (autograd)
+# ---------------------------------------------------------------------------
+
+def _run_traj(mesh, X_host, E_tet, target, steps, dt, tol, k, d0=None):
+    fem = mesh.fem
+    sim = adjoint.Simulation(fem=fem, steps=steps, dt=dt, tol=tol, maxit=2000, checkpoint_every=k)
+    Et = torch.as_tensor(E_tet, dtype=torch.float64).cuda().requires_grad_(True)
+    d0 = torch.zeros(3, mesh.nv, dtype=torch.float64, device="cuda") if d0 is None else d0.clone()
+    d0.requires_grad_(True)
+    v0 = torch.zeros(3, mesh.nv, dtype=torch.float64, device="cuda")
+    X = mesh.to_dev(X_host)
+    dT, _vT = adjoint.trajectory(sim, d0, v0, Et)
+    L = adjoint.position_loss(X, dT, mesh.to_dev(target))
+    L.backward()
+    return float(L.detach()), d0.grad, Et.grad
+
+
+@pytest.mark.parametrize("mname,model", MODELS)
+def test_trajectory_grad_vs_oracle(mname, model):
+    m = mg.jitter(mg.kuhn_cube(6), 0.01, seed=0)
+    E_tet, target, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, ref = _pair(m, model, E_tet)
+    steps, dt, tol = 6, 1e-3, 1e-13
+    L, gd0, gE = _run_traj(mesh, m.X, E_tet, target, steps, dt, tol, k=2)
+    zero = np.zeros((m.nv, 3))
+    L_e, gd0_e, gE_e = oracle.trajectory_grad(ref, zero, zero, steps, dt, tol, 2000, target, m.X,
+                                              checkpoint_every=0)
+    assert abs(L - L_e) <= 1e-10 * abs(L_e)
+    assert nerr(_host(gd0), gd0_e) < 1e-8
+    assert nerr(gE.cpu().numpy(), gE_e) < 1e-8
+
+
+def test_trajectory_grad_checkpoint_invariance():
+    # deterministic block strategy: recomputed segments are bitwise equal to the forward,
+    # so every checkpoint spacing gives the same gradient bit for bit
+    m = mg.jitter(mg.kuhn_cube(5), 0.01, seed=0)
+    E_tet, target, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, _ = _pair(m, oracle.NH, E_tet, strategy="block")
+    res = [_run_traj(mesh, m.X, E_tet, target, 7, 1e-3, 1e-10, k) for k in (0, 1, 2, 3, 7)]
+    for L, gd, gE in res[1:]:
+        assert L == res[0][0]
+        assert torch.equal(gd, res[0][1])
+        assert torch.equal(gE, res[0][2])
+
+
+def _loss_diff(mesh, sim, X, target, d0, E_a, E_b):
+    """L(E_a) - L(E_b) computed from the two final states without cancellation in L."""
+    v0 = torch.zeros_like(d0)
+    da, _ = adjoint.trajectory(sim, d0, v0, E_a)
+    db, _ = adjoint.trajectory(sim, d0, v0, E_b)
+    return float(((da - db) * (da + db + 2.0 * (X - target))).sum())
+
+
+def test_trajectory_grad_central_differences_full_size():
+    """48^3 cube (663,552 tets), neo-Hookean, per-tet log-normal E, 20 steps of dt=1e-3 with CG to
+    1e-10, checkpoints every 5 steps: dL/dE on 32 sampled tets and dL/dd0 along one direction
+    against central differences (relative step 1e-3)."""
+    m = mg.kuhn_cube(48)
+    E_tet, target, fd_tets = mg.adjoint_recipe(m, seed=2, n_fd=32)
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.NH, elem_prec=ebbx.F64, E=1e5, nu=0.3, E_tet=E_tet,
+                        strategy=ebbx.STRAT_BLOCK)
+    steps, dt, tol = 20, 1e-3, 1e-10
+    L, gd0, gE = _run_traj(mesh, m.X, E_tet, target, steps, dt, tol, k=5)
+    assert np.isfinite(L) and float(gE.abs().max()) > 0
+    sim = adjoint.Simulation(fem=mesh.fem, steps=steps, dt=dt, tol=tol, maxit=2000, checkpoint_every=0)
+    X = mesh.to_dev(m.X)
+    tgt = mesh.to_dev(target)
+    d0 = torch.zeros(3, mesh.nv, dtype=torch.float64, device="cuda")
+    E0 = torch.as_tensor(E_tet, dtype=torch.float64).cuda()
+    fd = np.zeros(len(fd_tets))
+    for i, t in enumerate(fd_tets):
+        h = 1e-3 * E_tet[t]
+        Ep, Em = E0.clone(), E0.clone()
+        Ep[t] += h
+        Em[t] -= h
+        fd[i] = _loss_diff(mesh, sim, X, tgt, d0, Ep, Em) / (2 * h)
+    adj = gE.cpu().numpy()[fd_tets]
+    assert nerr(adj, fd) < 1e-4, (adj[:4], fd[:4])
+    # initial displacement along a random smooth direction
+    u = mesh.to_dev(1e-3 * mg.direction(m, 13))
+    eps = 1e-3
+    v0 = torch.zeros_like(d0)
+    da, _ = adjoint.trajectory(sim, d0 + eps * u, v0, E0)
+    db, _ = adjoint.trajectory(sim, d0 - eps * u, v0, E0)
+    fd_u = float(((da - db) * (da + db + 2.0 * (X - tgt))).sum()) / (2 * eps)
+    adj_u = float((gd0 * u).sum())
+    assert abs(adj_u - fd_u) <= 1e-5 * abs(fd_u)
+
+
+def test_step_vjp_full_size_vs_oracle():
+    """One step VJP at the 48^3 size (663,552 tets, per-tet E) against the oracle's, on the state
+    after one forward step."""
+    m = mg.kuhn_cube(48)
+    E_tet, target, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, ref = _pair(m, oracle.NH, E_tet, strategy="block")
+    d0 = np.zeros((m.nv, 3))
+    dt = 1e-3
+    _d1, v1, _dv, _st = ref.implicit_step(d0, d0, dt, tol=1e-12, maxit=2000)
+    gx = 2.0 * (m.X + 0.0 - target)
+    gv = np.zeros_like(gx)
+    db_e, vb_e, Eb_e, _ = ref.step_vjp(d0, v1, gx, gv, dt, tol=1e-12, maxit=2000)
+    E_bar = torch.zeros(m.nt, dtype=torch.float64, device="cuda")
+    db, vb, st = mesh.fem.step_vjp(_dev(d0), _dev(v1), _dev(gx), _dev(gv), dt, tol=1e-12, maxit=2000,
+                                   E_bar=E_bar)
+    assert ebbx.stats_fetch(st).status == ebbx.OK
+    assert nerr(_host(db), db_e) < 1e-9
+    assert nerr(_host(vb), vb_e) < 1e-9
+    assert nerr(E_bar.cpu().numpy(), Eb_e) < 1e-9
