@@ -71,6 +71,7 @@ enum {
 typedef enum { EBBX_F32 = 0, EBBX_F64 = 1, EBBX_I32 = 2, EBBX_U8 = 3, EBBX_I64 = 4 } ebbx_dtype;
 typedef struct ebbx_relation_s *ebbx_relation;
 typedef struct ebbx_fem_s *ebbx_fem;
+typedef struct ebbx_batch_s *ebbx_batch;
 typedef void *ebbx_stream;   /* hipStream_t */
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -258,10 +259,12 @@ typedef struct {
  *   or z = r; stop when ||r|| <= tol ||Pi b|| or after maxit iterations;
  *   then v += dv, d += dt v.
  * d and v are FP64 (3, nv), updated in place.  CG scalars and dot products
- * stay in FP64 on the device; the iterations run as one captured HIP graph
- * (no host synchronisation).  stats_dev (device, nullable) receives the
- * report.  If the solve breaks down (p^T A p <= 0) d and v are left
- * unchanged.  EBBX_E_PHASE if d and v alias. */
+ * stay in FP64 on the device; the iterations are replayed from captured HIP
+ * graphs in chunks of up to 128.  With tol = 0 nothing synchronises the
+ * host; with tol > 0 the host reads the device's convergence flag between
+ * chunks.  stats_dev (device, nullable) receives the report.  If the solve
+ * breaks down (p^T A p <= 0) d and v are left unchanged.  EBBX_E_PHASE if
+ * d and v alias; EBBX_E_STATE on the union domain of a batch. */
 ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
                                ebbx_step_stats *stats_dev, ebbx_stream stream);
 
@@ -300,6 +303,43 @@ ebbx_status ebbx_implicit_step_vjp(ebbx_fem fem, const double *d_n, const double
                                    const ebbx_step_params *params, const double *gx, const double *gv,
                                    double *d_bar, double *v_bar, double *E_bar, ebbx_step_stats *stats_dev,
                                    ebbx_stream stream);
+
+/* ---- batches of meshes ---------------------------------------------------- */
+
+/* Many independent meshes in one set of relations (the relational model's
+ * answer to batching: one `meshes` relation, key-fields tets.mesh and
+ * verts.mesh into it).  Layout contract: verts and tets are sorted by mesh
+ * id (non-decreasing), every tet's corners lie in the tet's mesh, and the
+ * meshes relation holds FP64 fields E and nu (one value per mesh). */
+typedef struct {
+    const char *tet_verts;   /* key-field tets -> verts, arity 4 */
+    const char *tet_mesh;    /* key-field tets -> meshes, arity 1 */
+    const char *vert_mesh;   /* key-field verts -> meshes, arity 1 */
+    const char *pos;         /* verts: FP64 x3 rest positions */
+    const char *pinned;      /* verts: U8 x1 Dirichlet mask, nullable */
+    const char *E;           /* meshes: FP64 x1 Young's modulus */
+    const char *nu;          /* meshes: FP64 x1 Poisson ratio */
+} ebbx_batch_fields;
+
+/* Build the union domain of all meshes (model, element precision, rho,
+ * strategy and block from params; params->E, nu ignored, E_field must be
+ * NULL).  Synchronous.  EBBX_E_LAYOUT if the layout contract is broken,
+ * EBBX_E_ARG for a mesh with E <= 0 or nu outside (-1, 0.5). */
+ebbx_status ebbx_batch_create(ebbx_relation meshes, ebbx_relation tets, ebbx_relation verts,
+                              const ebbx_batch_fields *fields, const ebbx_fem_params *params, ebbx_batch *out);
+ebbx_status ebbx_batch_destroy(ebbx_batch batch);
+
+/* The union domain (owned by the batch; ebbx_fem_destroy on it fails): the
+ * element calls (forces, Kmul, diag, energy) act on every mesh at once. */
+ebbx_status ebbx_batch_fem(ebbx_batch batch, ebbx_fem *out);
+
+/* One implicit step (as ebbx_implicit_step) of every mesh, each with its
+ * own CG scalars, stopping test and report: the meshes share every kernel
+ * launch, and a mesh that has converged skips its share of the vector work.
+ * per_mesh_dev: device array of nm ebbx_step_stats (nullable).  d and v are
+ * FP64 (3, nv) over the union's vertices. */
+ebbx_status ebbx_batch_implicit_step(ebbx_batch batch, double *d, double *v, const ebbx_step_params *params,
+                                     ebbx_step_stats *per_mesh_dev, ebbx_stream stream);
 
 /* Copy a device stats record to the host; synchronises the stream. */
 ebbx_status ebbx_stats_fetch(const ebbx_step_stats *stats_dev, ebbx_step_stats *host,

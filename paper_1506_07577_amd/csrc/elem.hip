@@ -450,7 +450,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a) {
         }
     T h[12];
     const bool ok = eval_tet<T, MODEL, OP>(mu, lam, b, V0, qd, qu, h, qw);
-    if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv, 1ull);
+    if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
     if (SC == SC_ATOMIC) {
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -629,7 +629,7 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
                 }
             T h[12];
             const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
-            if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv, 1ull);
+            if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
             if (RED == 0) {
 #pragma unroll
                 for (int j = 0; j < 12; ++j) s_h[j * BT + tl] = h[j];
@@ -803,6 +803,7 @@ static ElemArgs base_args(ebbx_fem_s *F) {
     a.mu = F->mu;
     a.lam = F->lam;
     a.n_inv = F->status.as<unsigned long long>();
+    a.tmesh = F->tmesh;
     a.blk_vptr = F->blk_vptr.as<int32_t>();
     a.blk_verts = F->blk_verts.as<int32_t>();
     a.blk_lptr = F->blk_lptr.as<int32_t>();

@@ -24,7 +24,8 @@ struct ElemArgs {
     const double *w[3];         // second direction columns (`w` of T[a, w])
     double *out[3];             // reduce target columns
     void *part;                 // (nt, 12) per-corner partials (segmented reduction)
-    unsigned long long *n_inv;  // inverted-element counter
+    unsigned long long *n_inv;  // inverted-element counters (one per mesh)
+    const int32_t *tmesh;       // per-tet mesh ids selecting the counter, or NULL (one mesh)
     // block strategy
     const int32_t *blk_vptr;    // (nblk + 1) offsets into blk_verts
     const int32_t *blk_verts;   // global vertex ids per block, sorted
@@ -57,6 +58,22 @@ void fill_f64(double *p, int64_t n, double v, hipStream_t s);
 // Build the tet-block tables of the BLOCK strategy.
 void build_blocks(ebbx_fem_s *F, int32_t tets_per_block, hipStream_t s);
 
+// FEM handle registry (fem.hip).
+ebbx_fem_s *check_fem(ebbx_fem f);
+void fem_register(ebbx_fem_s *F);
+void fem_unregister(ebbx_fem_s *F);
+// Validate and build a FEM domain (synchronous); E_tet: per-tet modulus or NULL.
+std::unique_ptr<ebbx_fem_s> fem_build(ebbx_relation_s *tr, const char *keyfield, ebbx_relation_s *vr,
+                                      const char *pos_field, const char *pinned_field, const ebbx_fem_params &p,
+                                      const double *E_tet);
+// Drop the captured solver graphs (solve.hip); they bake in kernel arguments.
+void step_drop_graphs(ebbx_fem_s *F);
+
+inline bool overlap(const void *a, const void *b, size_t bytes) {
+    const char *x = (const char *)a, *y = (const char *)b;
+    return x < y + bytes && y < x + bytes;
+}
+
 }  // namespace ebbx
 
 struct ebbx_fem_s {
@@ -69,6 +86,11 @@ struct ebbx_fem_s {
     double rho = 1000.0, E = 1e5, nu = 0.3, mu = 0.0, lam = 0.0;
     bool per_tet = false;
     const double *E_tet = nullptr;   // borrowed per-tet Young's modulus (nullable)
+    // meshes of a batch: vertex ranges [mesh_vptr[m], mesh_vptr[m+1]); one mesh otherwise
+    int64_t nm = 1;
+    std::vector<int64_t> mesh_vptr;
+    const int32_t *tmesh = nullptr;  // per-tet mesh ids (batch) or NULL
+    bool batch_owned = false;        // the union domain of a batch: destroyed with it
     size_t esize = 8;   // bytes of one element-precision value
 
     ebbx::DevBuf B, V0, mat, mass, pinned, part, status, scratch;
@@ -87,5 +109,6 @@ struct ebbx_fem_s {
     // implicit-step state (allocated on first step)
     struct Step;
     std::unique_ptr<Step> step;
+    ebbx_fem_s();   // both defined where Step is complete (solve.hip)
     ~ebbx_fem_s();
 };

@@ -1,0 +1,749 @@
+// solve.hip -- the implicit-Euler step, its adjoint, and batches of meshes.
+//
+// The step is the linearised backward-Euler step of the paper's Vega
+// workload (Performance Evaluation, Vega: an implicit integrator that builds
+// a linear system from the force and stiffness evaluations and solves it with
+// a Jacobi-preconditioned conjugate gradient), written as data-parallel
+// kernels over the vertex DOFs.
+//
+// Every solve is segmented by mesh: the DOFs of a domain are split into
+// chunks of at most VT vertices that never straddle two meshes, and each
+// mesh carries its own CG scalars on the device.  A plain domain is one
+// mesh; a batch is the union of many meshes whose solves run side by side in
+// the same kernels, each stopping on its own tolerance.  Dot products are
+// two-pass reductions: the first pass is fused into the vector kernels
+// (per-chunk partial sums, wavefront shuffles then LDS; Runtime
+// Implementation, "Reductions"), the second sums a mesh's chunk partials in
+// a fixed order, so results are reproducible run to run.  The iterations are
+// captured once into HIP graphs and replayed.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+
+#include "fem.h"
+
+namespace ebbx {
+
+// CG state of one mesh, kept on the device.
+struct CGState {
+    double rz, rr, pq, alpha, beta, bnorm;
+    int iters, status, done, converged;
+    unsigned long long n_inv;
+};
+
+// Solve-wide flags: meshes still iterating; all_done = 1 once none is.
+struct SolveCtl {
+    int n_active, all_done;
+};
+
+constexpr int VT = 256;   // threads of the vertex kernels = vertices per chunk
+
+// Chunks of the vertex range: chunk c covers vertices [lo[c], hi[c]) of mesh
+// mesh[c]; the chunks of mesh m are [cptr[m], cptr[m+1]).
+struct Chunks {
+    const int32_t *lo, *hi, *mesh, *cptr;
+};
+
+static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + VT - 1) / VT)); }
+
+// Sum of one double over a 256-thread block (fixed order).
+__device__ __forceinline__ double block_sum(double x, double *s4) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
+// Fixed-order sum of the partials (stride 2, offset o) of chunks [c0, c1).
+__device__ __forceinline__ double sum_parts(const double *part, int c0, int c1, int o, double *s4) {
+    double acc = 0.0;
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += VT) acc += part[2 * c + o];
+    return block_sum(acc, s4);
+}
+
+// One thread of the mesh's block marks it finished.
+__device__ __forceinline__ void mark_done(CGState &st, SolveCtl *ctl) {
+    st.done = 1;
+    if (atomicSub(&ctl->n_active, 1) == 1) ctl->all_done = 1;
+}
+
+struct StepVec {
+    double *dn, *vn, *f, *y, *r, *z, *p, *q, *x, *diag;
+};
+
+__global__ void k_step_begin(CGState *st, int nm, SolveCtl *ctl, unsigned long long *n_inv) {
+    for (int m = blockIdx.x * blockDim.x + threadIdx.x; m < nm; m += gridDim.x * blockDim.x) {
+        CGState &s = st[m];
+        s.rz = s.rr = s.pq = s.alpha = s.beta = s.bnorm = 0.0;
+        s.iters = 0;
+        s.status = EBBX_OK;
+        s.done = 0;
+        s.converged = 0;
+        s.n_inv = 0;
+        n_inv[m] = 0ull;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->n_active = nm;
+        ctl->all_done = nm == 0;
+    }
+}
+
+// b = dt (f + M g + dt K v); diag = M - dt^2 Kdiag (1 on pinned rows); r = Pi b;
+// z = D^-1 r; p = z; x = 0; chunk partials (r.z, r.r)
+// mode 0 (step): b = dt (f + M g + dt y), with f = f(d_n) and y = K(d_n) v_n;
+// mode 1 (adjoint solve): b = f, the right-hand side placed in f beforehand.
+__global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
+                                                 double dt, double gx, double gy, double gz, int precond, int mode,
+                                                 Chunks ch, double *part) {
+    __shared__ double s4[4];
+    const int c = blockIdx.x;
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (v < ch.hi[c]) {
+        const double m = mass[v];
+        const bool pin = pinned[v] != 0;
+        const double g[3] = {gx, gy, gz};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            const double b = mode ? w.f[i] : dt * (w.f[i] + m * g[k] + dt * w.y[i]);
+            const double dg = pin ? 1.0 : (precond ? m - dt * dt * w.diag[i] : 1.0);
+            const double r = pin ? 0.0 : b;
+            const double z = r / dg;
+            w.diag[i] = dg;
+            w.r[i] = r;
+            w.z[i] = z;
+            w.p[i] = z;
+            w.x[i] = 0.0;
+            rz += r * z;
+            rr += r * r;
+        }
+    }
+    rz = block_sum(rz, s4);
+    rr = block_sum(rr, s4);
+    if (threadIdx.x == 0) {
+        part[2 * c] = rz;
+        part[2 * c + 1] = rr;
+    }
+}
+
+// per mesh: initial r.z and |b|; inverted elements or b = 0 finish the mesh at once
+__global__ __launch_bounds__(VT) void k_step_init(CGState *st, const double *part, Chunks ch,
+                                                  const unsigned long long *n_inv, SolveCtl *ctl) {
+    __shared__ double s4[4];
+    const int m = blockIdx.x;
+    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 0, s4);
+    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 1, s4);
+    if (threadIdx.x == 0) {
+        CGState &s = st[m];
+        s.rz = rz;
+        s.rr = rr;
+        s.bnorm = sqrt(rr);
+        s.n_inv = n_inv[m];
+        if (s.n_inv > 0) {
+            s.status = EBBX_E_INVERTED;
+            mark_done(s, ctl);
+        } else if (rr == 0.0) {
+            s.converged = 1;
+            mark_done(s, ctl);
+        }
+    }
+}
+
+// q = Pi (M p - dt^2 y); chunk partial p.q
+__global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
+                                              double dt, const CGState *st, Chunks ch, double *part) {
+    __shared__ double s4[4];
+    const int c = blockIdx.x;
+    if (st[ch.mesh[c]].done) return;   // uniform over the block
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    double pq = 0.0;
+    if (v < ch.hi[c]) {
+        const double m = mass[v];
+        const bool pin = pinned[v] != 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            const double p = w.p[i];
+            const double q = pin ? 0.0 : m * p - dt * dt * w.y[i];
+            w.q[i] = q;
+            pq += p * q;
+        }
+    }
+    pq = block_sum(pq, s4);
+    if (threadIdx.x == 0) part[2 * c] = pq;
+}
+
+__global__ __launch_bounds__(VT) void k_cg_alpha(CGState *st, const double *part, Chunks ch, SolveCtl *ctl) {
+    __shared__ double s4[4];
+    const int m = blockIdx.x;
+    if (st[m].done) return;
+    const double pq = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 0, s4);
+    if (threadIdx.x == 0) {
+        CGState &s = st[m];
+        s.pq = pq;
+        if (!(pq > 0.0)) {
+            s.status = EBBX_E_NOT_SPD;
+            mark_done(s, ctl);
+        } else {
+            s.alpha = s.rz / pq;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha q; z = D^-1 r; chunk partials (r.z, r.r)
+__global__ __launch_bounds__(VT) void k_cg_update(StepVec w, int64_t nv, const CGState *st, Chunks ch, double *part) {
+    __shared__ double s4[4];
+    const int c = blockIdx.x;
+    const CGState &s = st[ch.mesh[c]];
+    if (s.done) return;
+    const double alpha = s.alpha;
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (v < ch.hi[c]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            w.x[i] += alpha * w.p[i];
+            const double r = w.r[i] - alpha * w.q[i];
+            const double z = r / w.diag[i];
+            w.r[i] = r;
+            w.z[i] = z;
+            rz += r * z;
+            rr += r * r;
+        }
+    }
+    rz = block_sum(rz, s4);
+    rr = block_sum(rr, s4);
+    if (threadIdx.x == 0) {
+        part[2 * c] = rz;
+        part[2 * c + 1] = rr;
+    }
+}
+
+__global__ __launch_bounds__(VT) void k_cg_beta(CGState *st, const double *part, Chunks ch, double tol, int maxit,
+                                                SolveCtl *ctl) {
+    __shared__ double s4[4];
+    const int m = blockIdx.x;
+    if (st[m].done) return;
+    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 0, s4);
+    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 1, s4);
+    if (threadIdx.x == 0) {
+        CGState &s = st[m];
+        s.iters += 1;
+        s.rr = rr;
+        if (sqrt(rr) <= tol * s.bnorm || rz == 0.0) {
+            s.converged = 1;
+            mark_done(s, ctl);
+        } else {
+            s.beta = rz / s.rz;
+            s.rz = rz;
+            if (s.iters >= maxit) mark_done(s, ctl);
+        }
+    }
+}
+
+// p = z + beta p
+__global__ __launch_bounds__(VT) void k_cg_p(StepVec w, int64_t nv, const CGState *st, Chunks ch) {
+    const int c = blockIdx.x;
+    const CGState &s = st[ch.mesh[c]];
+    if (s.done) return;
+    const double beta = s.beta;
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    if (v < ch.hi[c])
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            w.p[i] = w.z[i] + beta * w.p[i];
+        }
+}
+
+__global__ void k_copy_in(const double *d, const double *v, double *dn, double *vn, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        dn[i] = d[i];
+        vn[i] = v[i];
+    }
+}
+
+__device__ __forceinline__ void write_stats(const CGState &s, double tol, ebbx_step_stats *out) {
+    int status = s.status;
+    if (status == EBBX_OK && !s.converged && tol > 0.0) status = EBBX_E_NOT_CONVERGED;
+    out->iters = s.iters;
+    out->status = status;
+    out->rel_res = s.bnorm > 0.0 ? sqrt(s.rr) / s.bnorm : 0.0;
+    out->n_inverted = (int64_t)s.n_inv;
+}
+
+// per chunk: v = v_n + x, d = d_n + dt v unless the mesh's solve broke down;
+// the first chunk of each mesh writes its stats record
+__global__ __launch_bounds__(VT) void k_step_end(StepVec w, int64_t nv, double dt, double tol, const CGState *st,
+                                                 Chunks ch, double *d, double *v, ebbx_step_stats *stats) {
+    const int c = blockIdx.x, m = ch.mesh[c];
+    const CGState &s = st[m];
+    const int64_t j = (int64_t)ch.lo[c] + threadIdx.x;
+    if (s.status == EBBX_OK && j < ch.hi[c])
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + j;
+            const double vv = w.vn[i] + w.x[i];
+            v[i] = vv;
+            d[i] = w.dn[i] + dt * vv;
+        }
+    if (stats && c == ch.cptr[m] && threadIdx.x == 0) write_stats(s, tol, stats + m);
+}
+
+// adjoint: d_n copied in, g^ = gv + dt gx into f (the solve's right-hand side)
+__global__ void k_vjp_prep(const double *d, const double *gx, const double *gv, double dt, StepVec w, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        w.dn[i] = d[i];
+        w.f[i] = gv[i] + dt * gx[i];
+    }
+}
+
+// adjoint: d_bar = gx + dt K w + dt^2 T[v', w];  v_bar = g^ + dt^2 K w
+// (K w in y, T[v', w] in q, g^ in f); stats of each mesh's adjoint solve
+__global__ __launch_bounds__(VT) void k_vjp_end(StepVec w, const double *gx, double dt, int64_t nv, const CGState *st,
+                                                Chunks ch, double tol, double *d_bar, double *v_bar,
+                                                ebbx_step_stats *stats) {
+    const int c = blockIdx.x, m = ch.mesh[c];
+    const int64_t j = (int64_t)ch.lo[c] + threadIdx.x;
+    if (j < ch.hi[c])
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + j;
+            const double kw = w.y[i];
+            d_bar[i] = gx[i] + dt * kw + dt * dt * w.q[i];
+            v_bar[i] = w.f[i] + dt * dt * kw;
+        }
+    if (stats && c == ch.cptr[m] && threadIdx.x == 0) write_stats(st[m], tol, stats + m);
+}
+
+// ---- batches: validation and per-tet material ----------------------------------------------
+
+// Counts layout violations: mesh ids decreasing along verts or tets, or a tet
+// whose corners lie in another mesh.
+__global__ void k_batch_check(const int32_t *vmesh, const int32_t *tmesh, const int32_t *keys, int64_t nv,
+                              int64_t nt, unsigned long long *bad) {
+    const int64_t n = std::max(nv, nt);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long e = 0;
+        if (i < nv && i > 0 && vmesh[i] < vmesh[i - 1]) ++e;
+        if (i < nt) {
+            const int32_t m = tmesh[i];
+            if (i > 0 && m < tmesh[i - 1]) ++e;
+            for (int c = 0; c < 4; ++c)
+                if (vmesh[keys[(int64_t)c * nt + i]] != m) ++e;
+        }
+        if (e) atomicAdd(bad, e);
+    }
+}
+
+__global__ void k_expand_material(const int32_t *tmesh, const double *E_m, const double *nu_m, int64_t nt,
+                                  double *E_t, double *nu_t, unsigned long long *bad) {
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t m = tmesh[t];
+        const double E = E_m[m], nu = nu_m[m];
+        if (!(E > 0.0) || !(nu > -1.0 && nu < 0.5)) atomicAdd(bad, 1ull);
+        E_t[t] = E;
+        nu_t[t] = nu;
+    }
+}
+
+}  // namespace ebbx
+
+using namespace ebbx;
+
+struct ebbx_fem_s::Step {
+    DevBuf vec, part, state, ctl, chunks;
+    StepVec w{};
+    Chunks ch{};
+    int nch = 0, nm = 1;
+    // graphs: preambles of the step (0) and of the adjoint solve (1), and a chunk of CG iterations
+    hipGraphExec_t pre[2] = {nullptr, nullptr}, chunk = nullptr;
+    hipGraph_t g_pre[2] = {nullptr, nullptr}, g_chunk = nullptr;
+    hipStream_t cap = nullptr;
+    int chunk_iters = 0;
+    // parameters baked into the graphs
+    double dt = -1, g[3] = {0, 0, 0}, tol = -1;
+    int maxit = -1, precond = -1, strategy = -1, block = -1;
+    int *h_done = nullptr;   // pinned host flag for convergence checks
+    void drop_graphs() {
+        for (int k = 0; k < 2; ++k) {
+            if (pre[k]) (void)hipGraphExecDestroy(pre[k]);
+            if (g_pre[k]) (void)hipGraphDestroy(g_pre[k]);
+            pre[k] = nullptr;
+            g_pre[k] = nullptr;
+        }
+        if (chunk) (void)hipGraphExecDestroy(chunk);
+        if (g_chunk) (void)hipGraphDestroy(g_chunk);
+        chunk = nullptr;
+        g_chunk = nullptr;
+    }
+    ~Step() {
+        drop_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+        if (h_done) (void)hipHostFree(h_done);
+    }
+};
+
+ebbx_fem_s::ebbx_fem_s() = default;
+ebbx_fem_s::~ebbx_fem_s() = default;
+
+namespace ebbx {
+void step_drop_graphs(ebbx_fem_s *F) {
+    if (F->step) F->step->drop_graphs();
+}
+}  // namespace ebbx
+
+namespace {
+
+void capture_begin(hipStream_t cap) { HIPCHK(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal)); }
+
+hipGraphExec_t capture_end(hipStream_t cap, hipGraph_t *g) {
+    HIPCHK(hipStreamEndCapture(cap, g));
+    hipGraphExec_t ex = nullptr;
+    HIPCHK(hipGraphInstantiate(&ex, *g, nullptr, nullptr, 0));
+    return ex;
+}
+
+// Capture the preamble of `mode` (0: step, 1: adjoint solve) and, if the
+// parameters changed, the CG chunk shared by both.
+void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
+    auto &S = *F->step;
+    const bool same = S.dt == p.dt && !std::memcmp(S.g, p.g, sizeof S.g) && S.tol == p.tol && S.maxit == p.maxit &&
+                      S.precond == p.precond && S.strategy == F->strategy && S.block == F->block && S.chunk;
+    if (!same) S.drop_graphs();
+    if (S.pre[mode] && S.chunk) return;
+    const int64_t nv = F->nv;
+    const int nch = S.nch, nm = S.nm;
+    CGState *st = S.state.as<CGState>();
+    SolveCtl *ctl = S.ctl.as<SolveCtl>();
+    double *part = S.part.as<double>();
+    unsigned long long *n_inv = F->status.as<unsigned long long>();
+    hipStream_t cs = S.cap;
+    // preamble: (step) forces and K v; Jacobi diagonal; rhs; initial residual
+    capture_begin(cs);
+    hipLaunchKernelGGL(k_step_begin, dim3((nm + VT - 1) / VT), dim3(VT), 0, cs, st, nm, ctl, n_inv);
+    if (mode == 0) {
+        elem_launch(F, OP_FORCE, S.w.dn, nullptr, S.w.f, 0, cs);
+        elem_launch(F, OP_KMUL, S.w.dn, S.w.vn, S.w.y, 0, cs);
+    }
+    if (p.precond == EBBX_PRECOND_JACOBI) elem_launch(F, OP_DIAG, S.w.dn, nullptr, S.w.diag, 0, cs);
+    hipLaunchKernelGGL(k_step_rhs, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(), nv,
+                       p.dt, p.g[0], p.g[1], p.g[2], p.precond, mode, S.ch, part);
+    hipLaunchKernelGGL(k_step_init, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch,
+                       (const unsigned long long *)n_inv, ctl);
+    HIPCHK(hipGetLastError());
+    S.pre[mode] = capture_end(cs, &S.g_pre[mode]);
+    if (!S.chunk) {
+        // a chunk of CG iterations; every kernel is predicated on its mesh's done
+        // flag, the element map on the solve-wide all_done flag
+        S.chunk_iters = std::max(1, std::min(p.maxit, 128));
+        capture_begin(cs);
+        for (int it = 0; it < S.chunk_iters; ++it) {
+            elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &ctl->all_done);
+            hipLaunchKernelGGL(k_cg_Ap, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
+                               nv, p.dt, (const CGState *)st, S.ch, part);
+            hipLaunchKernelGGL(k_cg_alpha, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, ctl);
+            hipLaunchKernelGGL(k_cg_update, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch, part);
+            hipLaunchKernelGGL(k_cg_beta, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, p.tol, p.maxit,
+                               ctl);
+            hipLaunchKernelGGL(k_cg_p, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch);
+        }
+        HIPCHK(hipGetLastError());
+        S.chunk = capture_end(cs, &S.g_chunk);
+    }
+    S.dt = p.dt;
+    std::memcpy(S.g, p.g, sizeof S.g);
+    S.tol = p.tol;
+    S.maxit = p.maxit;
+    S.precond = p.precond;
+    S.strategy = F->strategy;
+    S.block = F->block;
+}
+
+void check_step_params(const ebbx_step_params *params) {
+    if (!params) fail(EBBX_E_ARG, "params is NULL");
+    const ebbx_step_params &p = *params;
+    if (!(p.dt > 0.0)) fail(EBBX_E_ARG, "dt must be > 0");
+    if (p.maxit < 0) fail(EBBX_E_ARG, "maxit must be >= 0");
+    if (!(p.tol >= 0.0)) fail(EBBX_E_ARG, "tol must be >= 0");
+    if (p.precond != EBBX_PRECOND_NONE && p.precond != EBBX_PRECOND_JACOBI) fail(EBBX_E_ARG, "bad precond");
+}
+
+// Solver buffers and the chunk tables of the mesh segmentation (once per domain).
+void ensure_step(ebbx_fem_s *F, hipStream_t s) {
+    if (F->step) return;
+    const int64_t nv = F->nv, nm = F->nm;
+    auto S = std::make_unique<ebbx_fem_s::Step>();
+    const int64_t n3 = 3 * std::max<int64_t>(nv, 1);
+    S->vec.reset((size_t)n3 * 10 * sizeof(double), s);
+    double *b = S->vec.as<double>();
+    S->w = StepVec{b, b + n3, b + 2 * n3, b + 3 * n3, b + 4 * n3, b + 5 * n3, b + 6 * n3, b + 7 * n3, b + 8 * n3,
+                   b + 9 * n3};
+    // chunks: every mesh gets at least one (possibly empty) so that it reports stats
+    std::vector<int32_t> lo, hi, mesh, cptr(1, 0);
+    for (int64_t m = 0; m < nm; ++m) {
+        const int64_t a = F->mesh_vptr[m], e = F->mesh_vptr[m + 1];
+        int64_t v = a;
+        do {
+            const int64_t w = std::min<int64_t>(v + VT, e);
+            lo.push_back((int32_t)v);
+            hi.push_back((int32_t)w);
+            mesh.push_back((int32_t)m);
+            v = w;
+        } while (v < e);
+        cptr.push_back((int32_t)lo.size());
+    }
+    const int64_t nch = (int64_t)lo.size();
+    if (nch >= (int64_t(1) << 31)) fail(EBBX_E_ARG, "too many vertex chunks");
+    S->nch = (int)nch;
+    S->nm = (int)nm;
+    S->chunks.reset((size_t)(3 * nch + nm + 1) * sizeof(int32_t), s);
+    int32_t *cp = S->chunks.as<int32_t>();
+    HIPCHK(hipMemcpyAsync(cp, lo.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cp + nch, hi.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cp + 2 * nch, mesh.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cp + 3 * nch, cptr.data(), (nm + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    S->ch = Chunks{cp, cp + nch, cp + 2 * nch, cp + 3 * nch};
+    S->part.reset((size_t)nch * 2 * sizeof(double), s);
+    S->state.reset((size_t)std::max<int64_t>(nm, 1) * sizeof(CGState), s);
+    S->ctl.reset(sizeof(SolveCtl), s);
+    HIPCHK(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
+    HIPCHK(hipHostMalloc((void **)&S->h_done, sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipStreamSynchronize(s));
+    F->step = std::move(S);
+}
+
+// Launch the preamble of `mode` and the CG chunks on s.
+void run_solve(ebbx_fem_s *F, const ebbx_step_params &p, int mode, hipStream_t s) {
+    build_graphs(F, p, mode);
+    auto &S = *F->step;
+    HIPCHK(hipGraphLaunch(S.pre[mode], s));
+    const int nchunks = p.maxit > 0 ? (p.maxit + S.chunk_iters - 1) / S.chunk_iters : 0;
+    SolveCtl *ctl = S.ctl.as<SolveCtl>();
+    for (int c = 0; c < nchunks; ++c) {
+        HIPCHK(hipGraphLaunch(S.chunk, s));
+        // with a tolerance, stop launching once every mesh has finished
+        if (p.tol > 0.0 && c + 1 < nchunks) {
+            HIPCHK(hipMemcpyAsync(S.h_done, &ctl->all_done, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (*S.h_done) break;
+        }
+    }
+}
+
+// One implicit step of every mesh of F; stats: one record per mesh (nullable).
+void implicit_step(ebbx_fem_s *F, double *d, double *v, const ebbx_step_params *params, ebbx_step_stats *stats,
+                   hipStream_t s) {
+    check_step_params(params);
+    const ebbx_step_params &p = *params;
+    const int64_t nv = F->nv;
+    if (nv > 0 && (!d || !v)) fail(EBBX_E_ARG, "d or v is NULL");
+    if (nv > 0 && overlap(d, v, (size_t)(3 * nv) * sizeof(double))) fail(EBBX_E_PHASE, "d aliases v");
+    ensure_step(F, s);
+    auto &S = *F->step;
+    if (nv > 0) {
+        hipLaunchKernelGGL(k_copy_in, dim3(grid_for(3 * nv)), dim3(VT), 0, s, (const double *)d, (const double *)v,
+                           S.w.dn, S.w.vn, 3 * nv);
+        HIPCHK(hipGetLastError());
+    }
+    run_solve(F, p, 0, s);
+    hipLaunchKernelGGL(k_step_end, dim3(S.nch), dim3(VT), 0, s, S.w, nv, p.dt, p.tol,
+                       (const CGState *)S.state.as<CGState>(), S.ch, d, v, stats);
+    HIPCHK(hipGetLastError());
+}
+
+}  // namespace
+
+extern "C" ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
+                                          ebbx_step_stats *stats_dev, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    if (F->nm != 1) fail(EBBX_E_STATE, "this domain is a batch of %lld meshes: use ebbx_batch_implicit_step",
+                         (long long)F->nm);
+    implicit_step(F, d, v, params, stats_dev, (hipStream_t)stream);
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_implicit_step_vjp(ebbx_fem fem, const double *d_n, const double *v_np1,
+                                              const ebbx_step_params *params, const double *gx, const double *gv,
+                                              double *d_bar, double *v_bar, double *E_bar,
+                                              ebbx_step_stats *stats_dev, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    if (F->nm != 1) fail(EBBX_E_STATE, "the adjoint step takes a single-mesh domain");
+    check_step_params(params);
+    const ebbx_step_params &p = *params;
+    const int64_t nv = F->nv;
+    if (nv > 0 && (!d_n || !v_np1 || !gx || !gv || !d_bar || !v_bar)) fail(EBBX_E_ARG, "a vector argument is NULL");
+    const size_t bytes = (size_t)(3 * nv) * sizeof(double);
+    if (nv > 0) {
+        const void *ins[4] = {d_n, v_np1, gx, gv};
+        for (const void *o : {(const void *)d_bar, (const void *)v_bar})
+            for (const void *i : ins)
+                if (overlap(o, i, bytes)) fail(EBBX_E_PHASE, "an output of the adjoint aliases an input");
+        if (overlap(d_bar, v_bar, bytes)) fail(EBBX_E_PHASE, "d_bar aliases v_bar");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ensure_step(F, s);
+    auto &S = *F->step;
+    if (nv > 0) {
+        hipLaunchKernelGGL(k_vjp_prep, dim3(grid_for(3 * nv)), dim3(VT), 0, s, d_n, gx, gv, p.dt, S.w, 3 * nv);
+        HIPCHK(hipGetLastError());
+    }
+    // A w = Pi (gv + dt gx), with A = M - dt^2 K(d_n); w ends in x
+    run_solve(F, p, 1, s);
+    elem_launch(F, OP_KMUL, S.w.dn, S.w.x, S.w.y, 0, s);
+    elem_launch(F, OP_TMUL, S.w.dn, v_np1, S.w.q, 0, s, nullptr, S.w.x);
+    hipLaunchKernelGGL(k_vjp_end, dim3(S.nch), dim3(VT), 0, s, S.w, gx, p.dt, nv,
+                       (const CGState *)S.state.as<CGState>(), S.ch, p.tol, d_bar, v_bar, stats_dev);
+    HIPCHK(hipGetLastError());
+    if (E_bar) elem_egrad(F, S.w.dn, v_np1, S.w.x, p.dt, E_bar, s);
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_stats_fetch(const ebbx_step_stats *stats_dev, ebbx_step_stats *host, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    if (!stats_dev || !host) fail(EBBX_E_ARG, "stats pointer is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemcpyAsync(host, stats_dev, sizeof(ebbx_step_stats), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    EBBX_API_END
+}
+
+// ---- batches ------------------------------------------------------------------------------
+
+struct ebbx_batch_s {
+    std::unique_ptr<ebbx_fem_s> fem;   // the union domain
+    ebbx_relation_s *meshes = nullptr;
+    DevBuf E_t, nu_t;                  // per-tet material expanded from the meshes' fields
+    ~ebbx_batch_s() {
+        if (fem) fem_unregister(fem.get());
+    }
+};
+
+namespace {
+std::mutex g_batch_mu;
+std::set<ebbx_batch_s *> g_batches;
+
+ebbx_batch_s *check_batch(ebbx_batch b) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (!b || !g_batches.count(b)) fail(EBBX_E_ARG, "invalid batch handle");
+    return b;
+}
+
+KeyField &mesh_key(ebbx_relation_s *r, const char *name, ebbx_relation_s *meshes) {
+    if (!name) fail(EBBX_E_ARG, "a mesh key-field name is NULL");
+    KeyField &k = get_key(r, name);
+    if (k.target != meshes) fail(EBBX_E_ARG, "key-field '%s' does not target '%s'", name, meshes->name.c_str());
+    if (k.arity != 1) fail(EBBX_E_SHAPE, "key-field '%s' must have arity 1", name);
+    return k;
+}
+}  // namespace
+
+extern "C" {
+
+ebbx_status ebbx_batch_create(ebbx_relation meshes, ebbx_relation tets, ebbx_relation verts,
+                              const ebbx_batch_fields *fields, const ebbx_fem_params *params, ebbx_batch *out) {
+    EBBX_API_BEGIN
+    if (!out) fail(EBBX_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!fields || !params) fail(EBBX_E_ARG, "fields or params is NULL");
+    if (params->E_field) fail(EBBX_E_ARG, "a batch takes its material from the meshes relation (E_field must be NULL)");
+    auto *mr = check_rel(meshes);
+    auto *tr = check_rel(tets);
+    auto *vr = check_rel(verts);
+    const int64_t nm = mr->size;
+    if (nm < 1) fail(EBBX_E_ARG, "a batch needs at least one mesh");
+    if (!fields->E || !fields->nu) fail(EBBX_E_ARG, "the meshes' E and nu field names are required");
+    const double *E_m = (const double *)get_field(mr, fields->E, EBBX_F64, 1).ptr;
+    const double *nu_m = (const double *)get_field(mr, fields->nu, EBBX_F64, 1).ptr;
+    KeyField &tk = mesh_key(tr, fields->tet_mesh, mr);
+    KeyField &vk = mesh_key(vr, fields->vert_mesh, mr);
+    hipStream_t s = nullptr;
+    auto B = std::make_unique<ebbx_batch_s>();
+    B->meshes = mr;
+    // the union domain, first with a placeholder uniform material
+    ebbx_fem_params up = *params;
+    up.E = 1.0;
+    up.nu = 0.25;
+    B->fem = fem_build(tr, fields->tet_verts, vr, fields->pos, fields->pinned, up, nullptr);
+    ebbx_fem_s *F = B->fem.get();
+    const int64_t nt = F->nt, nv = F->nv;
+    // layout: verts and tets sorted by mesh, every tet inside its mesh
+    DevBuf bad(2 * sizeof(unsigned long long), s);
+    HIPCHK(hipMemsetAsync(bad.get(), 0, 2 * sizeof(unsigned long long), s));
+    if (std::max(nt, nv) > 0) {
+        hipLaunchKernelGGL(k_batch_check, dim3(grid_for(std::max(nt, nv))), dim3(VT), 0, s, vk.ptr, tk.ptr, F->keys, nv,
+                           nt, bad.as<unsigned long long>());
+        HIPCHK(hipGetLastError());
+    }
+    // per-tet material from the meshes' E and nu
+    B->E_t.reset((size_t)std::max<int64_t>(nt, 1) * sizeof(double), s);
+    B->nu_t.reset((size_t)std::max<int64_t>(nt, 1) * sizeof(double), s);
+    if (nt > 0) {
+        hipLaunchKernelGGL(k_expand_material, dim3(grid_for(nt)), dim3(VT), 0, s, tk.ptr, E_m, nu_m, nt,
+                           B->E_t.as<double>(), B->nu_t.as<double>(), bad.as<unsigned long long>() + 1);
+        HIPCHK(hipGetLastError());
+    }
+    unsigned long long hbad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(hbad, bad.get(), sizeof hbad, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad[0]) fail(EBBX_E_LAYOUT, "batch layout: verts and tets must be sorted by mesh and every tet must lie in its "
+                      "mesh (%llu violations)", hbad[0]);
+    if (hbad[1]) fail(EBBX_E_ARG, "a mesh has E <= 0 or nu outside (-1, 0.5)");
+    elem_set_material(F, B->E_t.as<double>(), B->nu_t.as<double>(), 0.0, 0.0, s);
+    // vertex ranges of the meshes: the grouping of verts by mesh (sorted, so contiguous)
+    auto grp = build_group(vr, fields->vert_mesh, s);
+    F->mesh_vptr.assign((size_t)nm + 1, 0);
+    HIPCHK(hipMemcpyAsync(F->mesh_vptr.data(), grp->row_ptr.get(), (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                          s));
+    F->nm = nm;
+    F->tmesh = tk.ptr;
+    F->status.reset((size_t)std::max<int64_t>(nm, 4) * sizeof(unsigned long long), s);
+    HIPCHK(hipMemsetAsync(F->status.get(), 0, (size_t)std::max<int64_t>(nm, 4) * sizeof(unsigned long long), s));
+    F->batch_owned = true;
+    HIPCHK(hipStreamSynchronize(s));
+    fem_register(F);
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        g_batches.insert(B.get());
+    }
+    *out = B.release();
+    EBBX_API_END
+}
+
+ebbx_status ebbx_batch_destroy(ebbx_batch batch) {
+    EBBX_API_BEGIN
+    auto *B = check_batch(batch);
+    HIPCHK(hipDeviceSynchronize());
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        g_batches.erase(B);
+    }
+    delete B;
+    EBBX_API_END
+}
+
+ebbx_status ebbx_batch_fem(ebbx_batch batch, ebbx_fem *out) {
+    EBBX_API_BEGIN
+    if (!out) fail(EBBX_E_ARG, "out is NULL");
+    *out = check_batch(batch)->fem.get();
+    EBBX_API_END
+}
+
+ebbx_status ebbx_batch_implicit_step(ebbx_batch batch, double *d, double *v, const ebbx_step_params *params,
+                                     ebbx_step_stats *per_mesh_dev, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *B = check_batch(batch);
+    implicit_step(B->fem.get(), d, v, params, per_mesh_dev, (hipStream_t)stream);
+    EBBX_API_END
+}
+
+}  // extern "C"

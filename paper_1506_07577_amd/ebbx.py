@@ -50,6 +50,10 @@ class StepStats(C.Structure):
                 ("n_inverted", C.c_int64)]
 
 
+class BatchFields(C.Structure):
+    _fields_ = [(n, C.c_char_p) for n in ("tet_verts", "tet_mesh", "vert_mesh", "pos", "pinned", "E", "nu")]
+
+
 _lib = None
 _ALLOC_T = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 _FREE_T = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
@@ -107,6 +111,10 @@ def lib():
         "ebbx_fem_E_grad": ([P, P, P, P, D, P, P], I32_),
         "ebbx_fem_set_material": ([P, P, P, D, D, P], I32_),
         "ebbx_implicit_step_vjp": ([P, P, P, C.POINTER(StepParams), P, P, P, P, P, P, P], I32_),
+        "ebbx_batch_create": ([P, P, P, C.POINTER(BatchFields), C.POINTER(FemParams), C.POINTER(P)], I32_),
+        "ebbx_batch_destroy": ([P], I32_),
+        "ebbx_batch_fem": ([P, C.POINTER(P)], I32_),
+        "ebbx_batch_implicit_step": ([P, P, P, C.POINTER(StepParams), P, P], I32_),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -233,10 +241,22 @@ class Fem:
         self.model, self.elem_prec = model, elem_prec
         self.E, self.nu = float(E), float(nu)
 
+    @classmethod
+    def _borrowed(cls, h, tets: Relation, verts: Relation, model: int, elem_prec: int):
+        """A view of a domain owned by something else (a batch's union)."""
+        self = cls.__new__(cls)
+        self.h = h
+        self.tets, self.verts = tets, verts
+        self.nt, self.nv = tets.size, verts.size
+        self.model, self.elem_prec = model, elem_prec
+        self.E, self.nu = 0.0, 0.0
+        self._owned = False
+        return self
+
     def close(self):
-        if self.h:
+        if self.h and getattr(self, "_owned", True):
             _check(lib().ebbx_fem_destroy(self.h))
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -354,6 +374,83 @@ class Fem:
         _check(lib().ebbx_implicit_step(self.h, _ptr(d), _ptr(v), C.byref(p), _ptr(stats),
                                         _stream(stream)))
         return stats
+
+
+class Batch:
+    """Many meshes in one set of relations (see ebbx_batch_create)."""
+
+    def __init__(self, meshes: Relation, tets: Relation, verts: Relation, model: int, elem_prec: int,
+                 tet_verts="v", tet_mesh="mesh", vert_mesh="mesh", pos="X", pinned: Optional[str] = "pinned",
+                 E="E", nu="nu", rho=1000.0, strategy=STRAT_BLOCK, block=0):
+        f = BatchFields(tet_verts.encode(), tet_mesh.encode(), vert_mesh.encode(), pos.encode(),
+                        pinned.encode() if pinned else None, E.encode(), nu.encode())
+        p = FemParams(model, elem_prec, rho, 0.0, 0.0, None, strategy, block)
+        h = C.c_void_p()
+        _check(lib().ebbx_batch_create(meshes.h, tets.h, verts.h, C.byref(f), C.byref(p), C.byref(h)))
+        self.h = h
+        self.meshes, self.tets, self.verts = meshes, tets, verts
+        self.nm = meshes.size
+        hf = C.c_void_p()
+        _check(lib().ebbx_batch_fem(self.h, C.byref(hf)))
+        self.fem = Fem._borrowed(hf, tets, verts, model, elem_prec)
+
+    def implicit_step(self, d, v, dt, g=(0.0, 0.0, -9.81), tol=1e-8, maxit=1000, precond=PRECOND_JACOBI,
+                      stats=None, stream=None):
+        """Advance every mesh in place; returns the (nm, 3) int64 device stats tensor."""
+        self.fem._vec(d, "d")
+        self.fem._vec(v, "v")
+        if stats is None:
+            stats = torch.zeros(self.nm, 3, dtype=torch.int64, device=d.device)
+        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond))
+        _check(lib().ebbx_batch_implicit_step(self.h, _ptr(d), _ptr(v), C.byref(p), _ptr(stats), _stream(stream)))
+        return stats
+
+    def close(self):
+        if self.h:
+            self.fem.h = None
+            _check(lib().ebbx_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchMesh:
+    """Convenience: upload a meshgen.MeshUnion with per-mesh E and nu and build its Batch."""
+
+    def __init__(self, un, E, nu, model=NH, elem_prec=F32, rho=1000.0, strategy=STRAT_BLOCK, block=0):
+        self.un = un
+        nm = len(un.vptr) - 1
+        self.meshes = Relation("meshes", nm)
+        self.verts = Relation("verts", un.nv)
+        self.tets = Relation("tets", un.nt)
+        self.meshes.bind_field("E", torch.as_tensor(E, dtype=torch.float64).contiguous().cuda())
+        self.meshes.bind_field("nu", torch.as_tensor(nu, dtype=torch.float64).contiguous().cuda())
+        self.verts.bind_field("X", torch.as_tensor(un.X, dtype=torch.float64).t().contiguous().cuda())
+        self.verts.bind_field("pinned", torch.as_tensor(un.pinned).to(torch.uint8).contiguous().cuda())
+        self.verts.bind_keyfield("mesh", self.meshes, torch.as_tensor(un.vert_mesh).to(torch.int32).cuda())
+        self.tets.bind_keyfield("v", self.verts, torch.as_tensor(un.tets).to(torch.int32).t().contiguous().cuda())
+        self.tets.bind_keyfield("mesh", self.meshes, torch.as_tensor(un.tet_mesh).to(torch.int32).cuda())
+        self.batch = Batch(self.meshes, self.tets, self.verts, model, elem_prec, rho=rho, strategy=strategy,
+                           block=block)
+        self.fem = self.batch.fem
+        self.nm, self.nv, self.nt = nm, un.nv, un.nt
+
+    def to_dev(self, a):
+        return torch.as_tensor(a, dtype=torch.float64).t().contiguous().cuda()
+
+    @staticmethod
+    def from_dev(t):
+        return t.t().cpu().numpy()
+
+
+def stats_parse(stats_dev: torch.Tensor):
+    """(n, 3) int64 device stats records -> list of StepStats (one copy, syncs)."""
+    raw = stats_dev.reshape(-1, 3).cpu().numpy()
+    return [StepStats.from_buffer_copy(raw[i].tobytes()) for i in range(raw.shape[0])]
 
 
 def stats_fetch(stats_dev: torch.Tensor, stream=None) -> StepStats:

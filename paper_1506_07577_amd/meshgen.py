@@ -199,6 +199,51 @@ def batch_recipe(count: int = 256, seed: int = 3, nmin: int = 8, nmax: int = 40)
     return ns.astype(np.int64), E, nu
 
 
+@dataclass
+class MeshUnion:
+    """Meshes concatenated into one vertex set and one tet set, each sorted by
+    mesh: the layout of a batch (vertex and tet ids offset per mesh)."""
+    X: np.ndarray            # (sum nv, 3)
+    tets: np.ndarray         # (sum nt, 4) int32, global vertex ids
+    pinned: np.ndarray       # (sum nv,) uint8
+    vert_mesh: np.ndarray    # (sum nv,) int32
+    tet_mesh: np.ndarray     # (sum nt,) int32
+    vptr: np.ndarray         # (count + 1,) vertex offsets
+    tptr: np.ndarray         # (count + 1,) tet offsets
+
+    @property
+    def nv(self) -> int:
+        return int(self.X.shape[0])
+
+    @property
+    def nt(self) -> int:
+        return int(self.tets.shape[0])
+
+
+def union(meshes) -> MeshUnion:
+    nvs = np.array([m.nv for m in meshes], dtype=np.int64)
+    nts = np.array([m.nt for m in meshes], dtype=np.int64)
+    vptr = np.concatenate([[0], np.cumsum(nvs)])
+    tptr = np.concatenate([[0], np.cumsum(nts)])
+    if vptr[-1] >= 2 ** 31 or tptr[-1] >= 2 ** 31:
+        raise ValueError("union too large for int32 ids")
+    X = np.concatenate([m.X for m in meshes]).astype(np.float64, copy=False)
+    tets = np.concatenate([m.tets for m in meshes]).astype(np.int32, copy=False)
+    tets += np.repeat(vptr[:-1], nts).astype(np.int32)[:, None]
+    pinned = np.concatenate([m.pinned for m in meshes]).astype(np.uint8, copy=False)
+    vert_mesh = np.repeat(np.arange(len(meshes), dtype=np.int32), nvs)
+    tet_mesh = np.repeat(np.arange(len(meshes), dtype=np.int32), nts)
+    return MeshUnion(X, tets, pinned, vert_mesh, tet_mesh, vptr, tptr)
+
+
+def workload_batch(count: int = 256, seed: int = 3, nmin: int = 8, nmax: int = 40):
+    """Batched workload: `count` Kuhn cubes with sides from batch_recipe,
+    compressible neo-Hookean, per-mesh E and nu, dt = 1e-3, CG to 1e-8,
+    at most 1000 iterations.  Returns (meshes, E, nu)."""
+    ns, E, nu = batch_recipe(count, seed, nmin, nmax)
+    return [kuhn_cube(int(n)) for n in ns], E, nu
+
+
 def adjoint_recipe(mesh: Mesh, seed: int = 2, n_fd: int = 32):
     """Per-tet E = 1e5 exp(0.5 z), target = X + 1e-3 N(0,1), and n_fd
     distinct tets for finite-difference checks, in that draw order."""
