@@ -24,6 +24,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -53,7 +55,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--strategy", default="block", choices=["atomic", "seg", "block", "block_lds"])
+    ap.add_argument("--strategy", default="block", choices=["atomic", "seg", "block", "block_lds", "owner"])
     ap.add_argument("--order", default="morton", choices=["lattice", "morton"])
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--block", type=int, default=0,
@@ -64,7 +66,115 @@ def parse():
     ap.add_argument("--all-strategies", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-step section")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint section")
     return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def time_events(fn, stream, reps):
+    """Run fn() reps times, each bracketed by HIP events on `stream`; returns ms per run."""
+    import torch
+    out = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return out
+
+
+def bench_batch(stream, plain_rate):
+    """256 Kuhn cubes (sides 8..40), neo-Hookean, FP32 elements, per-mesh E and nu,
+    one implicit step of every mesh with per-mesh CG to 1e-8 (maxit 1000)."""
+    import torch
+
+    from paper_1506_07577_amd import ebbx
+    from paper_1506_07577_amd import meshgen as mg
+    t0 = time.perf_counter()
+    meshes, E, nu = mg.workload_batch()
+    un = mg.union(meshes)
+    del meshes
+    bm = ebbx.BatchMesh(un, E, nu, model=ebbx.NH, elem_prec=ebbx.F32)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    log(f"batch: {bm.nm} meshes, {bm.nt} tets, {bm.nv} verts, setup {setup:.1f} s")
+    d0 = torch.zeros(3, bm.nv, dtype=torch.float64, device="cuda")
+    d, v = d0.clone(), d0.clone()
+    stats = torch.zeros(bm.nm, 3, dtype=torch.int64, device="cuda")
+
+    def step():
+        bm.batch.implicit_step(d, v, 1e-3, tol=1e-8, maxit=1000, stats=stats, stream=stream)
+
+    def reset():
+        d.zero_()
+        v.zero_()
+
+    reset()
+    step()   # graph capture
+    times = []
+    for _ in range(3):
+        reset()
+        times += time_events(step, stream, 1)
+    st = ebbx.stats_parse(stats)
+    nts = np.diff(un.tptr)
+    iters = np.array([s.iters for s in st])
+    ms = min(times)
+    useful = float(np.sum(nts * iters))
+    rate = useful / (ms * 1e-3)
+    return {"meshes": bm.nm, "tets": bm.nt, "verts": bm.nv, "setup_s": round(setup, 1),
+            "step_ms": round(ms, 3), "cg_iters_min": int(iters.min()), "cg_iters_max": int(iters.max()),
+            "cg_iters_mean": round(float(iters.mean()), 2),
+            "all_converged": bool(all(s.status == ebbx.OK for s in st)),
+            "max_rel_res": max(s.rel_res for s in st),
+            "tet_cg_iters_per_s": round(rate, 1),
+            "vs_plain_tet_cg_iters_per_s": round(rate / plain_rate, 4) if plain_rate else None}
+
+
+def bench_adjoint(stream, plain_rate):
+    """48^3 cube, neo-Hookean FP64, per-tet log-normal E: 20 implicit steps (CG to 1e-10)
+    forward, then dL/dE and dL/dd0 of ||x_T - target||^2 with checkpoints every 5 steps."""
+    import torch
+
+    from paper_1506_07577_amd import adjoint, ebbx
+    from paper_1506_07577_amd import meshgen as mg
+    m = mg.kuhn_cube(48)
+    E_tet, target, _ = mg.adjoint_recipe(m, seed=2)
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.NH, elem_prec=ebbx.F64, E=1e5, nu=0.3, E_tet=E_tet,
+                        strategy=ebbx.STRAT_BLOCK)
+    sim = adjoint.Simulation(fem=mesh.fem, steps=20, dt=1e-3, tol=1e-10, maxit=2000, checkpoint_every=5)
+    X = mesh.to_dev(m.X)
+    tgt = mesh.to_dev(target)
+    Et = torch.as_tensor(E_tet, dtype=torch.float64).cuda()
+
+    def run():
+        d0 = torch.zeros(3, mesh.nv, dtype=torch.float64, device="cuda", requires_grad=True)
+        v0 = torch.zeros(3, mesh.nv, dtype=torch.float64, device="cuda")
+        Eg = Et.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dT, _ = adjoint.trajectory(sim, d0, v0, Eg)
+        L = adjoint.position_loss(X, dT, tgt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+
+    run()   # graph capture
+    fw, bw = min(run() for _ in range(3))
+    return {"tets": mesh.nt, "verts": mesh.nv, "steps": 20, "checkpoint_every": 5,
+            "forward_ms": round(1e3 * fw, 2), "backward_ms": round(1e3 * bw, 2),
+            "backward_over_forward": round(bw / fw, 3),
+            "note": "wall clock with device syncs; forward = 20 implicit steps (CG to 1e-10), backward = "
+                    "segment recompute + 20 step VJPs (adjoint CG, K w, T[v, w], dL/dE)"}
 
 
 def main():
@@ -85,7 +195,7 @@ def main():
     w = mg.workload_plain(args.n)
     m = w.mesh
     strat_id = {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-                "block_lds": ebbx.STRAT_BLOCK_LDS}
+                "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER}
     t_setup = time.perf_counter()
     mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=w.model, elem_prec=ebbx.F32, E=w.E, nu=w.nu,
                         strategy=strat_id[args.strategy], block=args.block, morton=(args.order == "morton"))
@@ -144,13 +254,14 @@ def main():
 
     others = {}
     if args.all_strategies:
-        for s in ["atomic", "seg", "block", "block_lds"]:
+        for s in ["atomic", "seg", "block", "block_lds", "owner"]:
             if s != args.strategy:
                 r = measure(s, 0)
                 others[s] = {"cold_force_us": round(1e3 * statistics.median(r["tf"]), 2),
                              "cold_kmul_us": round(1e3 * statistics.median(r["tk"]), 2),
                              "warm_step_us": round(1e3 * r["warm_ms"], 2)}
     r = measure(args.strategy, args.block)
+    log(f"force+Kmul cold {statistics.mean(r['tf']) + statistics.mean(r['tk']):.4f} ms")
     tf_ms = statistics.mean(r["tf"])
     tk_ms = statistics.mean(r["tk"])
     ms_per_step = tf_ms + tk_ms
@@ -193,9 +304,20 @@ def main():
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
         s = ebbx.stats_fetch(st)
+        plain_rate = nt * s.iters / (min(times) * 1e-3)
         extra["implicit_step"] = {"ms": round(min(times), 3), "cg_iters": s.iters,
                                   "us_per_cg_iter": round(1e3 * min(times) / max(s.iters, 1), 2),
+                                  "tet_cg_iters_per_s": round(plain_rate, 1),
                                   "rel_res": s.rel_res, "status": s.status}
+        log(f"implicit step {min(times):.3f} ms")
+    else:
+        plain_rate = None
+    if not args.no_batch:
+        extra["batched"] = bench_batch(stream, plain_rate)
+        log(f"batched step {extra['batched']['step_ms']} ms")
+    if not args.no_adjoint:
+        extra["adjoint"] = bench_adjoint(stream, plain_rate)
+        log(f"adjoint fwd {extra['adjoint']['forward_ms']} ms bwd {extra['adjoint']['backward_ms']} ms")
 
     cpu = None
     if not args.no_cpu_baseline:

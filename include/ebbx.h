@@ -159,12 +159,20 @@ enum { EBBX_STVK = 0, EBBX_NH = 1 };
  *              deterministic;
  *   BLOCK_LDS: as BLOCK, but the in-block sums use FP64 LDS atomics (not
  *              bitwise reproducible);
- *   AUTO:      the library's choice.
+ *   OWNER:     each block owns a contiguous range of vertices (best after
+ *              Morton reordering) and evaluates every tet incident to them,
+ *              so a tet on a block boundary is evaluated once per block it
+ *              touches; each owned vertex sums its incidences in the
+ *              grouping's (tet, corner) order and is stored once: no halo,
+ *              no atomics, one kernel, results bitwise equal to SEG;
+ *   AUTO:      BLOCK with 256 tets per block (ebbx_fem_autotune times the
+ *              alternatives on the domain itself).
  * The `block` argument of the calls below is the workgroup size (threads) for
- * ATOMIC and SEG, and the number of tets per block (64..512, a power of two)
- * for BLOCK and BLOCK_LDS; 0 picks the default. */
+ * ATOMIC and SEG, the number of tets per block (64..512, a power of two)
+ * for BLOCK and BLOCK_LDS, and the owned vertices per block (64, 128 or
+ * 256) for OWNER; 0 picks the default. */
 enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3,
-       EBBX_STRAT_BLOCK_LDS = 4 };
+       EBBX_STRAT_BLOCK_LDS = 4, EBBX_STRAT_OWNER = 5 };
 
 typedef struct {
     int32_t model;       /* EBBX_STVK or EBBX_NH */
@@ -194,6 +202,25 @@ ebbx_status ebbx_fem_destroy(ebbx_fem fem);
 ebbx_status ebbx_fem_set_strategy(ebbx_fem fem, int32_t strategy, int32_t block);
 /* Read back the strategy and block size in use (after AUTO resolution). */
 ebbx_status ebbx_fem_get_strategy(ebbx_fem fem, int32_t *strategy, int32_t *block);
+
+/* Autotuner (solver kernels are block-size sensitive; Performance
+ * Evaluation, Vega): time the stiffness product at (d, u) under every
+ * strategy and a set of block sizes, keep the fastest.  d, u: FP64 (3, nv)
+ * device vectors or NULL (then d = 0, u = 1).  cache_path (nullable): a JSON
+ * file of earlier choices, one entry per line, keyed by the device, model,
+ * precision, material kind, sizes and a fingerprint of the tets' keys; a
+ * hit skips the timing, a miss adds the choice (EBBX_E_ARG if the file
+ * cannot be written).  results (nullable, room for cap entries) receives
+ * the timings in microseconds per call; *n_results the number timed (0 on a
+ * cache hit).  Synchronous; every candidate call overwrites library scratch
+ * only.  Captured solver graphs are rebuilt on the next step. */
+typedef struct {
+    int32_t strategy;
+    int32_t block;
+    double us;
+} ebbx_tune_entry;
+ebbx_status ebbx_fem_autotune(ebbx_fem fem, const double *d, const double *u, const char *cache_path,
+                              ebbx_tune_entry *results, int32_t cap, int32_t *n_results, ebbx_stream stream);
 
 /* Internal elastic force at displacement d (x = X + d): per tet G = dD B with
  * dD = [d1-d0 | d2-d0 | d3-d0], F = I + G, first Piola-Kirchhoff stress P(F)

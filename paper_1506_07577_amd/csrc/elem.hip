@@ -544,6 +544,12 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
     const uint32_t vb = (uint32_t)a.blk_vptr[blk];
     const uint32_t nvb = (uint32_t)a.blk_vptr[blk + 1] - vb;
     const uint32_t t0 = blk * BT;
+    if (a.mdone) {   // a batch: skip the block once every mesh it touches has finished (uniform)
+        const int32_t m0 = a.tmesh[t0], m1 = a.tmesh[min(t0 + BT, nt) - 1];
+        bool all = true;
+        for (int32_t m = m0; m <= m1; ++m) all = all && a.mdone[m] != 0;
+        if (all) return;
+    }
     // RED == 0: incidence lists + per-tet result rows (deterministic sums);
     // RED == 1: FP64 LDS atomics into one accumulator per block vertex
     uint16_t *s_list = (uint16_t *)s_dyn4;                       // 4 BT + 8 entries
@@ -672,6 +678,125 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
 }
 
 // Sum each shared vertex's halo entries (its blocks' partials, in block order).
+// OWNER strategy: workgroup = one block of owned vertices.  The block stages
+// the fields of its vertices (owned, then ghosts) in LDS, evaluates every tet
+// listed for it, writes the rows of owned corners to their positions in the
+// block's incidence order, and each owned vertex sums its contiguous run of
+// rows in FP64 (the grouping's (tet, corner) order) and stores the result.
+template <class T, int MODEL, int OP>
+__global__ __launch_bounds__(256) void k_owner(ElemArgs a) {
+    extern __shared__ double s_own[];
+    if (a.skip && *a.skip) return;   // uniform over the grid
+    const uint32_t tid = threadIdx.x;
+    const uint32_t blk = xcd_block(blockIdx.x, a.own_nblk);
+    const uint32_t v0 = blk * a.own_vb;
+    const uint32_t nown = min(a.own_vb, a.nv - v0);
+    const uint32_t g0 = (uint32_t)a.own_gptr[blk], ngh = (uint32_t)a.own_gptr[blk + 1] - g0;
+    const uint32_t nvb = nown + ngh;
+    const uint32_t tb = (uint32_t)a.own_tptr[blk], ntb = (uint32_t)a.own_tptr[blk + 1] - tb;
+    if (a.mdone && ntb > 0) {   // a batch: skip once every mesh of the block's tets has finished (uniform)
+        const int32_t m0 = a.tmesh[a.own_meta[tb].x], m1 = a.tmesh[a.own_meta[tb + ntb - 1].x];
+        bool all = true;
+        for (int32_t m = m0; m <= m1; ++m) all = all && a.mdone[m] != 0;
+        if (all) return;
+    }
+    const int64_t rbase = a.rp[v0];
+    const uint32_t ninc = (uint32_t)(a.rp[v0 + nown] - rbase);
+    constexpr int NQ = OP == OP_TMUL ? 3 : OP == OP_KMUL ? 2 : 1;
+    double *s_d = s_own;
+    double *s_u = s_d + 3 * nvb;
+    double *s_w = s_u + 3 * nvb;
+    T *s_h = (T *)(s_d + 3 * NQ * nvb);   // 3 columns of ninc rows
+    // this thread's owned vertex: its incidence run
+    uint32_t e0 = 0, e1 = 0;
+    if (tid < nown) {
+        e0 = (uint32_t)(a.rp[v0 + tid] - rbase);
+        e1 = (uint32_t)(a.rp[v0 + tid + 1] - rbase);
+    }
+    for (uint32_t i = tid; i < nvb; i += blockDim.x) {
+        const uint32_t gv = i < nown ? v0 + i : (uint32_t)a.own_ghost[g0 + i - nown];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_d[k * nvb + i] = ldc<double>(a.d[k], gv);
+            if (NQ > 1) s_u[k * nvb + i] = ldc<double>(a.u[k], gv);
+            if (NQ > 2) s_w[k * nvb + i] = ldc<double>(a.w[k], gv);
+        }
+    }
+    __syncthreads();
+    for (uint32_t j = tid; j < ntb; j += blockDim.x) {
+        const uint4 m = a.own_meta[tb + j];
+        const uint32_t t = m.x;
+        T b[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) b[k] = ldc<T>(a.B[k], t);
+        const T V0 = ldc<T>(a.V0, t);
+        T mu, lam;
+        if (a.mu_t) {
+            mu = ldc<T>(a.mu_t, t);
+            lam = ldc<T>(a.lam_t, t);
+        } else {
+            mu = (T)a.mu;
+            lam = (T)a.lam;
+        }
+        // corners: 24 bits each over (y, z, w): 11-bit slot | 13-bit position (0x1fff: not owned)
+        const uint64_t lo = (uint64_t)m.y | ((uint64_t)m.z << 32);
+        const uint32_t cw[4] = {(uint32_t)(lo & 0xffffffu), (uint32_t)((lo >> 24) & 0xffffffu),
+                                (uint32_t)((lo >> 48) | ((uint64_t)(m.w & 0xffu) << 16)), m.w >> 8};
+        double qd[4][3], qu[4][3], qw[4][3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t sl = cw[c] & 0x7ffu;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                qd[c][k] = s_d[k * nvb + sl];
+                qu[c][k] = (NQ > 1) ? s_u[k * nvb + sl] : 0.0;
+                qw[c][k] = (NQ > 2) ? s_w[k * nvb + sl] : 0.0;
+            }
+        }
+        T h[12];
+        const bool ok = eval_tet<T, MODEL, OP>(mu, lam, b, V0, qd, qu, h, qw);
+        // the block owning corner 0 counts an inverted tet (exactly once over all blocks)
+        if (MODEL == EBBX_NH && OP == OP_FORCE && !ok && (cw[0] >> 11) != 0x1fffu)
+            atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t p = cw[c] >> 11;
+            if (p != 0x1fffu) {
+                s_h[p] = h[3 * c];
+                s_h[ninc + p] = h[3 * c + 1];
+                s_h[2 * ninc + p] = h[3 * c + 2];
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < nown) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (uint32_t e = e0; e < e1; ++e) {
+            a0 += (double)s_h[e];
+            a1 += (double)s_h[ninc + e];
+            a2 += (double)s_h[2 * ninc + e];
+        }
+        const uint32_t gv = v0 + tid;
+        if (a.accumulate) {
+            a0 += ldc<double>(a.out[0], gv);
+            a1 += ldc<double>(a.out[1], gv);
+            a2 += ldc<double>(a.out[2], gv);
+        }
+        stc<double>(a.out[0], gv, a0);
+        stc<double>(a.out[1], gv, a1);
+        stc<double>(a.out[2], gv, a2);
+    }
+}
+
+template <class T, int MODEL>
+static void launch_owner(ElemOp op, const ElemArgs &a, unsigned grid, size_t shmem, hipStream_t s) {
+    if (op == OP_FORCE) hipLaunchKernelGGL((k_owner<T, MODEL, OP_FORCE>), dim3(grid), dim3(256), shmem, s, a);
+    else if (op == OP_KMUL) hipLaunchKernelGGL((k_owner<T, MODEL, OP_KMUL>), dim3(grid), dim3(256), shmem, s, a);
+    else if (op == OP_TMUL) hipLaunchKernelGGL((k_owner<T, MODEL, OP_TMUL>), dim3(grid), dim3(256), shmem, s, a);
+    else hipLaunchKernelGGL((k_owner<T, MODEL, OP_DIAG>), dim3(grid), dim3(256), shmem, s, a);
+    HIPCHK(hipGetLastError());
+}
+
 __global__ __launch_bounds__(256) void k_halo_reduce(const double *halo, const int32_t *sh_vert, const int32_t *sh_ptr,
                                                      const int32_t *sh_pos, uint32_t S, double *o0, double *o1,
                                                      double *o2, int accumulate, const int *skip) {
@@ -813,6 +938,13 @@ static ElemArgs base_args(ebbx_fem_s *F) {
     a.slot[1] = F->blk_local.as<uint32_t>() + (F->blk_w == 2 ? nt : 0);
     a.halo = F->halo.as<double>();
     a.nblk = (uint32_t)F->nblk;
+    a.own_tptr = F->own_tptr.as<int32_t>();
+    a.own_meta = F->own_meta.as<uint4>();
+    a.own_gptr = F->own_gptr.as<int32_t>();
+    a.own_ghost = F->own_ghost.as<int32_t>();
+    a.rp = F->group ? F->group->row_ptr.as<int64_t>() : nullptr;
+    a.own_vb = (uint32_t)F->own_vb;
+    a.own_nblk = (uint32_t)F->own_nblk;
     return a;
 }
 
@@ -828,7 +960,7 @@ size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
 }
 
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
-                 hipStream_t s, const int *skip, const double *w) {
+                 hipStream_t s, const int *skip, const double *w, const int *mdone) {
     const int64_t nt = F->nt, nv = F->nv;
     if (nv == 0) return;
     if (nt == 0) {
@@ -842,7 +974,24 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
     for (int k = 0; k < 3; ++k) a.out[k] = out + (size_t)k * nv;
     a.part = F->part.get();
     a.skip = skip;
+    a.mdone = F->tmesh ? mdone : nullptr;
     a.accumulate = accumulate;
+    if (F->strategy == EBBX_STRAT_OWNER) {
+        const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
+        const size_t shmem = (size_t)3 * nq * F->own_maxv * sizeof(double) + (size_t)3 * F->own_maxinc * F->esize;
+        if (shmem > 64 * 1024)
+            fail(EBBX_E_STATE, "owner strategy needs %zu bytes of LDS per block; use fewer vertices per block",
+                 shmem);
+        const unsigned grid = (unsigned)F->own_nblk;
+        if (F->prec == EBBX_F32) {
+            if (F->model == EBBX_STVK) launch_owner<float, EBBX_STVK>(op, a, grid, shmem, s);
+            else launch_owner<float, EBBX_NH>(op, a, grid, shmem, s);
+        } else {
+            if (F->model == EBBX_STVK) launch_owner<double, EBBX_STVK>(op, a, grid, shmem, s);
+            else launch_owner<double, EBBX_NH>(op, a, grid, shmem, s);
+        }
+        return;
+    }
     if (F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS) {
         const size_t shmem = block_shmem(F, op);
         if (shmem > 64 * 1024)
@@ -1261,6 +1410,93 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
     up(F->sh_pos, sh_pos.data(), sh_pos.size() * sizeof(int32_t));
     F->halo.reset(std::max<size_t>((size_t)F->halo_n * 3 * sizeof(double), 8), s);
     F->blocks_built = true;
+}
+
+// OWNER tables.  Block b owns vertices [b*vb, min(nv, (b+1)*vb)).  Its tets are
+// every tet incident to an owned vertex (ascending ids); its staged vertices
+// are the owned ones (local ids 0..nown-1) then the other vertices of its
+// tets (ascending).  The owned incidences, in the grouping's order (vertex,
+// then tet, then corner), give each owned corner of a listed tet its row in
+// the block's sum buffer; the kernel needs no other reduction metadata.
+void build_owner(ebbx_fem_s *F, int32_t vb, hipStream_t s) {
+    const int64_t nt = F->nt, nv = F->nv;
+    if (vb != 64 && vb != 128 && vb != 256)
+        fail(EBBX_E_ARG, "owner strategy: owned vertices per block must be 64, 128 or 256 (got %d)", vb);
+    const int64_t nblk = std::max<int64_t>(1, (nv + vb - 1) / vb);
+    std::vector<int32_t> keys((size_t)(4 * nt));
+    if (nt > 0) HIPCHK(hipMemcpy(keys.data(), F->keys, keys.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int64_t> rp((size_t)(nv + 1));
+    HIPCHK(hipMemcpy(rp.data(), F->group->row_ptr.get(), rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> inc((size_t)(4 * nt));
+    if (nt > 0) HIPCHK(hipMemcpy(inc.data(), F->group->inc.get(), inc.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int32_t> tptr((size_t)nblk + 1, 0), gptr((size_t)nblk + 1, 0), ghost;
+    std::vector<uint32_t> meta;   // 4 words per (block, tet)
+    std::vector<int32_t> tl, gl;
+    std::vector<uint32_t> pos;
+    int32_t maxv = 1, maxinc = 1;
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int64_t v0 = std::min<int64_t>(nv, b * vb), v1 = std::min<int64_t>(nv, v0 + vb);
+        const int64_t r0 = rp[(size_t)v0], r1 = rp[(size_t)v1];
+        tl.clear();
+        for (int64_t e = r0; e < r1; ++e) tl.push_back(inc[(size_t)e] >> 2);
+        std::sort(tl.begin(), tl.end());
+        tl.erase(std::unique(tl.begin(), tl.end()), tl.end());
+        gl.clear();
+        for (int32_t t : tl)
+            for (int c = 0; c < 4; ++c) {
+                const int32_t v = keys[(size_t)(c * nt + t)];
+                if (v < v0 || v >= v1) gl.push_back(v);
+            }
+        std::sort(gl.begin(), gl.end());
+        gl.erase(std::unique(gl.begin(), gl.end()), gl.end());
+        const int64_t nvb = (v1 - v0) + (int64_t)gl.size(), ninc = r1 - r0;
+        if (nvb > 2047) fail(EBBX_E_ARG, "owner block %lld stages %lld vertices (limit 2047); use fewer per block",
+                             (long long)b, (long long)nvb);
+        if (ninc > 8190) fail(EBBX_E_ARG, "owner block %lld has %lld owned incidences (limit 8190)", (long long)b,
+                              (long long)ninc);
+        maxv = std::max<int32_t>(maxv, (int32_t)nvb);
+        maxinc = std::max<int32_t>(maxinc, (int32_t)ninc);
+        pos.assign(4 * tl.size(), 0x1fffu);
+        for (int64_t e = r0; e < r1; ++e) {
+            const int32_t t = inc[(size_t)e] >> 2, c = inc[(size_t)e] & 3;
+            const size_t j = (size_t)(std::lower_bound(tl.begin(), tl.end(), t) - tl.begin());
+            pos[4 * j + c] = (uint32_t)(e - r0);
+        }
+        for (size_t j = 0; j < tl.size(); ++j) {
+            const int32_t t = tl[j];
+            uint32_t cw[4];
+            for (int c = 0; c < 4; ++c) {
+                const int32_t v = keys[(size_t)(c * nt + t)];
+                const uint32_t sl = (v >= v0 && v < v1)
+                                        ? (uint32_t)(v - v0)
+                                        : (uint32_t)((v1 - v0) + (std::lower_bound(gl.begin(), gl.end(), v) - gl.begin()));
+                cw[c] = sl | (pos[4 * j + c] << 11);
+            }
+            const uint64_t lo = (uint64_t)cw[0] | ((uint64_t)cw[1] << 24) | ((uint64_t)(cw[2] & 0xffffu) << 48);
+            meta.push_back((uint32_t)t);
+            meta.push_back((uint32_t)lo);
+            meta.push_back((uint32_t)(lo >> 32));
+            meta.push_back((cw[2] >> 16) | (cw[3] << 8));
+        }
+        ghost.insert(ghost.end(), gl.begin(), gl.end());
+        if (meta.size() / 4 >= (size_t)(1u << 31) || ghost.size() >= (size_t)(1u << 31))
+            fail(EBBX_E_ARG, "owner tables exceed int32");
+        tptr[(size_t)b + 1] = (int32_t)(meta.size() / 4);
+        gptr[(size_t)b + 1] = (int32_t)ghost.size();
+    }
+    F->own_vb = vb;
+    F->own_nblk = nblk;
+    F->own_maxv = maxv;
+    F->own_maxinc = maxinc;
+    F->own_ntb = (int64_t)(meta.size() / 4);
+    auto up = [&](DevBuf &dst, const void *src, size_t bytes) {
+        dst.reset(std::max<size_t>(bytes, 16), s);
+        if (bytes) HIPCHK(hipMemcpy(dst.get(), src, bytes, hipMemcpyHostToDevice));
+    };
+    up(F->own_tptr, tptr.data(), tptr.size() * sizeof(int32_t));
+    up(F->own_meta, meta.data(), meta.size() * sizeof(uint32_t));
+    up(F->own_gptr, gptr.data(), gptr.size() * sizeof(int32_t));
+    up(F->own_ghost, ghost.data(), ghost.size() * sizeof(int32_t));
 }
 
 }  // namespace ebbx

@@ -35,15 +35,25 @@ struct ElemArgs {
     const uint32_t *slot[2];    // packed corner slots within the block (one or two words per tet)
     double *halo;               // partial sums of shared vertices, 3 per entry, block-major
     uint32_t nblk;              // tet blocks
+    // owner strategy: block b owns vertices [b*own_vb, (b+1)*own_vb) and evaluates every
+    // tet incident to them (tets on a block boundary are evaluated by each block they touch)
+    const int32_t *own_tptr;    // (nblk + 1) offsets into own_meta
+    const uint4 *own_meta;      // per (block, tet): tet id, then 4 x (11-bit slot | 13-bit sum position)
+    const int32_t *own_gptr;    // (nblk + 1) offsets into own_ghost
+    const int32_t *own_ghost;   // staged vertices not owned by the block, ascending
+    const int64_t *rp;          // grouping row offsets (incidences of each vertex in (tet, corner) order)
+    uint32_t own_vb, own_nblk;
     int accumulate;             // 1: out += result
     const int *skip;            // nullable device flag: nonzero = return at once (converged solve)
+    const int *mdone;           // nullable per-mesh finished flags (batch): a block whose meshes are
+                                // all finished returns at once (block strategies)
 };
 
 // Launch the element map `op` with the FEM's current strategy; result into
 // out (3, nv) (+= if accumulate).  For OP_DIAG, u is ignored and out receives
 // the raw stiffness diagonal K[(v,c),(v,c)].
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
-                 hipStream_t s, const int *skip = nullptr, const double *w = nullptr);
+                 hipStream_t s, const int *skip = nullptr, const double *w = nullptr, const int *mdone = nullptr);
 // E_bar[t] += w_t . (dt f_t + dt^2 K_t v) / E_t over the tets (no scatter).
 void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double dt, double *E_bar,
                 hipStream_t s);
@@ -57,6 +67,8 @@ int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hip
 void fill_f64(double *p, int64_t n, double v, hipStream_t s);
 // Build the tet-block tables of the BLOCK strategy.
 void build_blocks(ebbx_fem_s *F, int32_t tets_per_block, hipStream_t s);
+// Build the vertex-owned block tables of the OWNER strategy.
+void build_owner(ebbx_fem_s *F, int32_t verts_per_block, hipStream_t s);
 
 // FEM handle registry (fem.hip).
 ebbx_fem_s *check_fem(ebbx_fem f);
@@ -66,6 +78,8 @@ void fem_unregister(ebbx_fem_s *F);
 std::unique_ptr<ebbx_fem_s> fem_build(ebbx_relation_s *tr, const char *keyfield, ebbx_relation_s *vr,
                                       const char *pos_field, const char *pinned_field, const ebbx_fem_params &p,
                                       const double *E_tet);
+// Select the scatter strategy and block size (builds block tables as needed).
+void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s);
 // Drop the captured solver graphs (solve.hip); they bake in kernel arguments.
 void step_drop_graphs(ebbx_fem_s *F);
 
@@ -105,6 +119,13 @@ struct ebbx_fem_s {
     int64_t halo_n = 0;        // halo entries
     ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_list, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos;
     bool blocks_built = false;
+    // owner strategy tables
+    int32_t own_vb = 0;        // owned vertices per block
+    int64_t own_nblk = 0;
+    int32_t own_maxv = 0;      // most staged vertices (owned + ghosts) of one block
+    int32_t own_maxinc = 0;    // most owned incidences of one block
+    int64_t own_ntb = 0;       // (block, tet) pairs over all blocks
+    ebbx::DevBuf own_tptr, own_meta, own_gptr, own_ghost;
 
     // implicit-step state (allocated on first step)
     struct Step;

@@ -45,8 +45,22 @@ void fem_unregister(ebbx_fem_s *F) {
 // `block`: threads per workgroup for ATOMIC and SEG (64..256, multiple of 64);
 // tets per block for BLOCK (64, 128, 256, 512 or 1024).  0 = default.
 void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s) {
-    if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_BLOCK_LDS) fail(EBBX_E_ARG, "bad strategy %d", strategy);
+    if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_OWNER) fail(EBBX_E_ARG, "bad strategy %d", strategy);
     if (strategy == EBBX_STRAT_AUTO) strategy = EBBX_STRAT_BLOCK;
+    if (strategy == EBBX_STRAT_OWNER) {
+        int32_t vb = block ? block : (F->prec == EBBX_F32 ? 128 : 64);
+        if (F->own_vb != vb) build_owner(F, vb, s);
+        // default size: fall back to 64 owned vertices when the stiffness product's
+        // LDS (staged d and u, and the owned rows) would exceed 64 KiB
+        const size_t kmul_lds = (size_t)6 * F->own_maxv * sizeof(double) + (size_t)3 * F->own_maxinc * F->esize;
+        if (!block && vb > 64 && kmul_lds > 64 * 1024) {
+            vb = 64;
+            build_owner(F, vb, s);
+        }
+        F->strategy = strategy;
+        F->block = vb;
+        return;
+    }
     if (strategy == EBBX_STRAT_BLOCK || strategy == EBBX_STRAT_BLOCK_LDS) {
         const int32_t bt = block ? block : 256;
         if (bt > 512) fail(EBBX_E_ARG, "block strategies take at most 512 tets per block");

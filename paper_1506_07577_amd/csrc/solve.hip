@@ -34,10 +34,13 @@ struct CGState {
     unsigned long long n_inv;
 };
 
-// Solve-wide flags: meshes still iterating; all_done = 1 once none is.
+// Solve-wide flags: meshes still iterating; all_done = 1 once none is.  The
+// per-mesh finished flags (nm ints) follow the struct in memory.
 struct SolveCtl {
     int n_active, all_done;
 };
+
+__device__ __forceinline__ int *mesh_done(SolveCtl *c) { return (int *)(c + 1); }
 
 constexpr int VT = 256;   // threads of the vertex kernels = vertices per chunk
 
@@ -66,9 +69,10 @@ __device__ __forceinline__ double sum_parts(const double *part, int c0, int c1, 
     return block_sum(acc, s4);
 }
 
-// One thread of the mesh's block marks it finished.
-__device__ __forceinline__ void mark_done(CGState &st, SolveCtl *ctl) {
+// One thread of the mesh's block marks mesh m finished.
+__device__ __forceinline__ void mark_done(CGState &st, SolveCtl *ctl, int m) {
     st.done = 1;
+    mesh_done(ctl)[m] = 1;
     if (atomicSub(&ctl->n_active, 1) == 1) ctl->all_done = 1;
 }
 
@@ -86,6 +90,7 @@ __global__ void k_step_begin(CGState *st, int nm, SolveCtl *ctl, unsigned long l
         s.converged = 0;
         s.n_inv = 0;
         n_inv[m] = 0ull;
+        mesh_done(ctl)[m] = 0;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctl->n_active = nm;
@@ -147,10 +152,10 @@ __global__ __launch_bounds__(VT) void k_step_init(CGState *st, const double *par
         s.n_inv = n_inv[m];
         if (s.n_inv > 0) {
             s.status = EBBX_E_INVERTED;
-            mark_done(s, ctl);
+            mark_done(s, ctl, m);
         } else if (rr == 0.0) {
             s.converged = 1;
-            mark_done(s, ctl);
+            mark_done(s, ctl, m);
         }
     }
 }
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(VT) void k_cg_alpha(CGState *st, const double *part
         s.pq = pq;
         if (!(pq > 0.0)) {
             s.status = EBBX_E_NOT_SPD;
-            mark_done(s, ctl);
+            mark_done(s, ctl, m);
         } else {
             s.alpha = s.rz / pq;
         }
@@ -239,11 +244,11 @@ __global__ __launch_bounds__(VT) void k_cg_beta(CGState *st, const double *part,
         s.rr = rr;
         if (sqrt(rr) <= tol * s.bnorm || rz == 0.0) {
             s.converged = 1;
-            mark_done(s, ctl);
+            mark_done(s, ctl, m);
         } else {
             s.beta = rz / s.rz;
             s.rz = rz;
-            if (s.iters >= maxit) mark_done(s, ctl);
+            if (s.iters >= maxit) mark_done(s, ctl, m);
         }
     }
 }
@@ -368,6 +373,7 @@ struct ebbx_fem_s::Step {
     hipGraph_t g_pre[2] = {nullptr, nullptr}, g_chunk = nullptr;
     hipStream_t cap = nullptr;
     int chunk_iters = 0;
+    bool valid = false;   // graphs match the parameters below
     // parameters baked into the graphs
     double dt = -1, g[3] = {0, 0, 0}, tol = -1;
     int maxit = -1, precond = -1, strategy = -1, block = -1;
@@ -383,6 +389,7 @@ struct ebbx_fem_s::Step {
         if (g_chunk) (void)hipGraphDestroy(g_chunk);
         chunk = nullptr;
         g_chunk = nullptr;
+        valid = false;
     }
     ~Step() {
         drop_graphs();
@@ -416,9 +423,9 @@ hipGraphExec_t capture_end(hipStream_t cap, hipGraph_t *g) {
 void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     auto &S = *F->step;
     const bool same = S.dt == p.dt && !std::memcmp(S.g, p.g, sizeof S.g) && S.tol == p.tol && S.maxit == p.maxit &&
-                      S.precond == p.precond && S.strategy == F->strategy && S.block == F->block && S.chunk;
+                      S.precond == p.precond && S.strategy == F->strategy && S.block == F->block && S.valid;
     if (!same) S.drop_graphs();
-    if (S.pre[mode] && S.chunk) return;
+    if (S.pre[mode]) return;
     const int64_t nv = F->nv;
     const int nch = S.nch, nm = S.nm;
     CGState *st = S.state.as<CGState>();
@@ -438,15 +445,13 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
                        p.dt, p.g[0], p.g[1], p.g[2], p.precond, mode, S.ch, part);
     hipLaunchKernelGGL(k_step_init, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch,
                        (const unsigned long long *)n_inv, ctl);
-    HIPCHK(hipGetLastError());
-    S.pre[mode] = capture_end(cs, &S.g_pre[mode]);
-    if (!S.chunk) {
-        // a chunk of CG iterations; every kernel is predicated on its mesh's done
-        // flag, the element map on the solve-wide all_done flag
-        S.chunk_iters = std::max(1, std::min(p.maxit, 128));
-        capture_begin(cs);
-        for (int it = 0; it < S.chunk_iters; ++it) {
-            elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &ctl->all_done);
+    // a chunk of CG iterations; every kernel is predicated on its mesh's done
+    // flag, the element map on the solve-wide all_done flag
+    S.chunk_iters = std::max(1, std::min(p.maxit, 128));
+    auto iterations = [&]() {
+        for (int it = 0; it < S.chunk_iters && it < p.maxit; ++it) {
+            elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &ctl->all_done, nullptr,
+                        nm > 1 ? (const int *)(ctl + 1) : nullptr);
             hipLaunchKernelGGL(k_cg_Ap, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
                                nv, p.dt, (const CGState *)st, S.ch, part);
             hipLaunchKernelGGL(k_cg_alpha, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, ctl);
@@ -455,9 +460,19 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
                                ctl);
             hipLaunchKernelGGL(k_cg_p, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch);
         }
+    };
+    // the preamble graph also holds the first chunk, so a solve that converges
+    // within it is one graph launch
+    iterations();
+    HIPCHK(hipGetLastError());
+    S.pre[mode] = capture_end(cs, &S.g_pre[mode]);
+    if (!S.chunk && p.maxit > S.chunk_iters) {
+        capture_begin(cs);
+        iterations();
         HIPCHK(hipGetLastError());
         S.chunk = capture_end(cs, &S.g_chunk);
     }
+    S.valid = true;
     S.dt = p.dt;
     std::memcpy(S.g, p.g, sizeof S.g);
     S.tol = p.tol;
@@ -513,7 +528,7 @@ void ensure_step(ebbx_fem_s *F, hipStream_t s) {
     S->ch = Chunks{cp, cp + nch, cp + 2 * nch, cp + 3 * nch};
     S->part.reset((size_t)nch * 2 * sizeof(double), s);
     S->state.reset((size_t)std::max<int64_t>(nm, 1) * sizeof(CGState), s);
-    S->ctl.reset(sizeof(SolveCtl), s);
+    S->ctl.reset(sizeof(SolveCtl) + (size_t)std::max<int64_t>(nm, 1) * sizeof(int), s);
     HIPCHK(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
     HIPCHK(hipHostMalloc((void **)&S->h_done, sizeof(int), hipHostMallocDefault));
     HIPCHK(hipStreamSynchronize(s));
@@ -524,17 +539,18 @@ void ensure_step(ebbx_fem_s *F, hipStream_t s) {
 void run_solve(ebbx_fem_s *F, const ebbx_step_params &p, int mode, hipStream_t s) {
     build_graphs(F, p, mode);
     auto &S = *F->step;
+    // preamble + first chunk, then further chunks until maxit
     HIPCHK(hipGraphLaunch(S.pre[mode], s));
     const int nchunks = p.maxit > 0 ? (p.maxit + S.chunk_iters - 1) / S.chunk_iters : 0;
     SolveCtl *ctl = S.ctl.as<SolveCtl>();
-    for (int c = 0; c < nchunks; ++c) {
-        HIPCHK(hipGraphLaunch(S.chunk, s));
+    for (int c = 1; c < nchunks; ++c) {
         // with a tolerance, stop launching once every mesh has finished
-        if (p.tol > 0.0 && c + 1 < nchunks) {
+        if (p.tol > 0.0) {
             HIPCHK(hipMemcpyAsync(S.h_done, &ctl->all_done, sizeof(int), hipMemcpyDeviceToHost, s));
             HIPCHK(hipStreamSynchronize(s));
             if (*S.h_done) break;
         }
+        HIPCHK(hipGraphLaunch(S.chunk, s));
     }
 }
 

@@ -23,7 +23,7 @@ E_DEGENERATE, E_INVERTED, E_NOT_SPD, E_NOT_CONVERGED, E_HIP, E_OOM, E_STATE, E_N
     -8, -9, -10, -11, -12, -13, -14, -15)
 F32, F64, I32, U8, I64 = 0, 1, 2, 3, 4
 STVK, NH = 0, 1
-STRAT_AUTO, STRAT_ATOMIC, STRAT_SEG, STRAT_BLOCK, STRAT_BLOCK_LDS = 0, 1, 2, 3, 4
+STRAT_AUTO, STRAT_ATOMIC, STRAT_SEG, STRAT_BLOCK, STRAT_BLOCK_LDS, STRAT_OWNER = 0, 1, 2, 3, 4, 5
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 
 _DT = {torch.float32: F32, torch.float64: F64, torch.int32: I32, torch.uint8: U8, torch.int64: I64}
@@ -48,6 +48,10 @@ class StepParams(C.Structure):
 class StepStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
                 ("n_inverted", C.c_int64)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("strategy", C.c_int32), ("block", C.c_int32), ("us", C.c_double)]
 
 
 class BatchFields(C.Structure):
@@ -111,6 +115,7 @@ def lib():
         "ebbx_fem_E_grad": ([P, P, P, P, D, P, P], I32_),
         "ebbx_fem_set_material": ([P, P, P, D, D, P], I32_),
         "ebbx_implicit_step_vjp": ([P, P, P, C.POINTER(StepParams), P, P, P, P, P, P, P], I32_),
+        "ebbx_fem_autotune": ([P, P, P, S, C.POINTER(TuneEntry), I32_, C.POINTER(I32_), P], I32_),
         "ebbx_batch_create": ([P, P, P, C.POINTER(BatchFields), C.POINTER(FemParams), C.POINTER(P)], I32_),
         "ebbx_batch_destroy": ([P], I32_),
         "ebbx_batch_fem": ([P, C.POINTER(P)], I32_),
@@ -271,6 +276,20 @@ class Fem:
         s, b = C.c_int32(), C.c_int32()
         _check(lib().ebbx_fem_get_strategy(self.h, C.byref(s), C.byref(b)))
         return s.value, b.value
+
+    def autotune(self, d=None, u=None, cache: Optional[str] = None, stream=None):
+        """Time the stiffness product under each strategy/block size and keep the fastest.
+        Returns [(strategy, block, us)] (empty on a cache hit)."""
+        if d is not None:
+            self._vec(d, "d")
+        if u is not None:
+            self._vec(u, "u")
+        cap = 64
+        arr = (TuneEntry * cap)()
+        n = C.c_int32()
+        _check(lib().ebbx_fem_autotune(self.h, _ptr(d), _ptr(u), cache.encode() if cache else None, arr, cap,
+                                       C.byref(n), _stream(stream)))
+        return [(arr[i].strategy, arr[i].block, arr[i].us) for i in range(min(n.value, cap))]
 
     def _vec(self, t, what):
         _dev(t, torch.float64, what)

@@ -40,13 +40,14 @@ def _gpu():
 
 def _strat(name):
     return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-            "block_lds": ebbx.STRAT_BLOCK_LDS}[name]
+            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER}[name]
 
 
 def _pair(m, model, E_tet, nu=0.3, prec="f64", strategy="block"):
     """GPU FemMesh and oracle FEM over the same mesh and per-tet material."""
     mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=model, elem_prec=ebbx.F64 if prec == "f64" else ebbx.F32,
-                        E=float(np.median(E_tet)), nu=nu, E_tet=E_tet, strategy=_strat(strategy))
+                        E=float(np.median(E_tet)), nu=nu, E_tet=E_tet, strategy=_strat(strategy),
+                        block=64 if strategy == "owner" else 0)
     ref = oracle.FEM.create(model, m.X, m.tets, E_tet, nu, pinned=m.pinned)
     return mesh, ref
 
@@ -66,7 +67,7 @@ MODELS = [("stvk", oracle.STVK), ("nh", oracle.NH)]
 # single evaluations
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("strategy", ["atomic", "seg", "block", "block_lds"])
+@pytest.mark.parametrize("strategy", ["atomic", "seg", "block", "block_lds", "owner"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("mname,model", MODELS)
 def test_tmul_parity(mname, model, prec, strategy):

@@ -19,12 +19,12 @@ else:  # collected on a CPU host only to be deselected
     ebbx = None
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
-STRATS = ["atomic", "seg", "block", "block_lds"]
+STRATS = ["atomic", "seg", "block", "block_lds", "owner"]
 
 
 def _strat(name):
     return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-            "block_lds": ebbx.STRAT_BLOCK_LDS}[name]
+            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER}[name]
 
 
 def _prec(p):
@@ -204,7 +204,7 @@ def test_morton_reordered_mesh_same_physics():
     mesh.fem.close()
 
 
-@pytest.mark.parametrize("strat", ["seg", "block"])
+@pytest.mark.parametrize("strat", ["seg", "block", "owner"])
 def test_deterministic_strategies_bitwise_reproducible(strat):
     m = _mesh_small()
     mesh, _ = _pair(m, 1, "f32", strat, morton=True)
