@@ -70,6 +70,10 @@ template <class T> __device__ __forceinline__ T det3(const T *A) {
            A[2] * (A[3] * A[7] - A[4] * A[6]);
 }
 
+// Rest volume from B = Dm^-1: V0 = det(Dm)/6 = 1/(6 det B).  The element maps
+// derive it instead of streaming a V0 column (one load fewer per tet).
+template <class T> __device__ __forceinline__ T tet_V0(const T *b) { return t_rcp(T(6) * det3(b)); }
+
 // C = A B
 template <class T> __device__ __forceinline__ void mul3(const T *A, const T *B, T *C) {
 #pragma unroll
@@ -427,7 +431,7 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a) {
     T b[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) b[k] = ldc<T>(a.B[k], t);
-    const T V0 = ldc<T>(a.V0, t);
+    const T V0 = tet_V0(b);
     T mu, lam;
     if (a.mu_t) {
         mu = ldc<T>(a.mu_t, t);
@@ -495,25 +499,23 @@ template <int W> __device__ __forceinline__ void unpack_slots(const ElemArgs &a,
     }
 }
 
-// LDS layout: the block's incidence lists (copied with 16-byte loads), the
-// block's vertex fields with one column per component (d, and u for the
-// stiffness product), then the per-tet results, one column per (corner,
-// component) pair, each tet writing its own row.  Each block vertex is then
-// summed by one thread over its incidence list (fixed order, FP64) and either
-// stored (the block owns the vertex) or written to the halo.  Every global
-// load that does not depend on another is issued at kernel start.
+// LDS layout: the block's vertex fields with one column per component (d, and
+// u for the stiffness product), then the per-corner results, three columns
+// (x, y, z) whose rows follow the block's incidence order (by vertex, then
+// local tet, then corner): each tet writes its four corners to the rows the
+// block tables give them, so every block vertex then sums one contiguous run
+// of rows (fixed order, FP64) and either stores it (the block owns the vertex)
+// or writes it to the halo.  Every global load that does not depend on another
+// is issued at kernel start.
 template <class T>
-__device__ __forceinline__ void reduce_slot(const ElemArgs &a, const uint16_t *s_list, const T *s_h, uint32_t BT,
-                                            uint32_t bsh, uint32_t gv, int32_t hp, int32_t j0, int32_t j1) {
+__device__ __forceinline__ void reduce_slot(const ElemArgs &a, const T *s_h, uint32_t LB, uint32_t gv, int32_t hp,
+                                            int32_t j0, int32_t j1) {
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll 4
-    for (int32_t j = j0; j < j1; ++j) {
-        const uint32_t e = s_list[j];   // c * BT + local tet
-        const uint32_t c = e >> bsh, tl = e & (BT - 1);
-        const T *p = s_h + 3 * c * BT + tl;
-        a0 += (double)p[0];
-        a1 += (double)p[BT];
-        a2 += (double)p[2 * BT];
+    for (int32_t j = j0; j < j1; ++j) {   // this vertex's rows, in (local tet, corner) order
+        a0 += (double)s_h[j];
+        a1 += (double)s_h[LB + j];
+        a2 += (double)s_h[2 * LB + j];
     }
     if (hp < 0) {
         // every incident tet is in this block: sole writer
@@ -539,10 +541,13 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
     if (a.skip && *a.skip) return;   // uniform over the grid
     const uint32_t nt = a.nt;
     const uint32_t tid = threadIdx.x, nthr = blockDim.x, BT = nthr * TPT;
-    const uint32_t bsh = 31u - __clz(BT);   // BT is a power of two
+    const uint32_t LB = 4 * BT;   // rows of one component column of the per-corner results
     const uint32_t blk = xcd_block(blockIdx.x, a.nblk);
-    const uint32_t vb = (uint32_t)a.blk_vptr[blk];
-    const uint32_t nvb = (uint32_t)a.blk_vptr[blk + 1] - vb;
+    // block tables at a fixed stride S (padded with vertex -1): no dependent offset load
+    const uint32_t S = a.blk_stride;
+    const int32_t *bverts = a.blk_verts + (size_t)blk * S;
+    const int32_t *bhpos = a.blk_hpos + (size_t)blk * S;
+    const uint16_t *brow = a.blk_row + (size_t)blk * (S + 1);
     const uint32_t t0 = blk * BT;
     if (a.mdone) {   // a batch: skip the block once every mesh it touches has finished (uniform)
         const int32_t m0 = a.tmesh[t0], m1 = a.tmesh[min(t0 + BT, nt) - 1];
@@ -550,38 +555,37 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
         for (int32_t m = m0; m <= m1; ++m) all = all && a.mdone[m] != 0;
         if (all) return;
     }
-    // RED == 0: incidence lists + per-tet result rows (deterministic sums);
+    // RED == 0: per-corner result rows in the block's incidence order (deterministic sums);
     // RED == 1: FP64 LDS atomics into one accumulator per block vertex
-    uint16_t *s_list = (uint16_t *)s_dyn4;                       // 4 BT + 8 entries
     constexpr int NQ = OP == OP_TMUL ? 3 : OP == OP_KMUL ? 2 : 1;   // staged vertex fields
-    double *s_d = (double *)((char *)s_dyn4 + (RED == 0 ? 8 * BT + 16 : 0));
-    double *s_u = s_d + 3 * nvb;
-    double *s_w = s_u + 3 * nvb;
-    T *s_h = (T *)(s_d + 3 * NQ * nvb);
+    double *s_d = (double *)s_dyn4;
+    double *s_u = s_d + 3 * S;
+    double *s_w = s_u + 3 * S;
+    T *s_h = (T *)(s_d + 3 * NQ * S);
     double *s_acc = (double *)s_h;
 
     // this thread's first block vertex
-    const bool has = tid < nvb;
-    uint32_t gv0 = 0;
+    const int32_t gvs0 = tid < S ? bverts[tid] : -1;
+    const bool has = gvs0 >= 0;
+    const uint32_t gv0 = has ? (uint32_t)gvs0 : 0u;
     int32_t hp0 = -1, j00 = 0, j10 = 0;
     if (has) {
-        gv0 = (uint32_t)a.blk_verts[vb + tid];
-        hp0 = a.blk_hpos[vb + tid];
+        hp0 = bhpos[tid];
         if (RED == 0) {
-            j00 = a.blk_lptr[vb + tid];
-            j10 = a.blk_lptr[vb + tid + 1];
+            j00 = brow[tid];
+            j10 = brow[tid + 1];
         }
     }
     // per-tet streams
     T b[TPT][9], V0[TPT], mu[TPT], lam[TPT];
-    uint32_t sl[TPT][4];
+    uint32_t sl[TPT][4], pw[TPT][2];
 #pragma unroll
     for (int r = 0; r < TPT; ++r) {
         const uint32_t t = t0 + r * nthr + tid;
         if (t < nt) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) b[r][k] = ldc<T>(a.B[k], t);
-            V0[r] = ldc<T>(a.V0, t);
+            V0[r] = tet_V0(b[r]);
             if (a.mu_t) {
                 mu[r] = ldc<T>(a.mu_t, t);
                 lam[r] = ldc<T>(a.lam_t, t);
@@ -590,33 +594,31 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
                 lam[r] = (T)a.lam;
             }
             unpack_slots<W>(a, t, sl[r]);
+            if (RED == 0) {
+                pw[r][0] = ldc<uint32_t>(a.blk_pos[0], t);
+                pw[r][1] = ldc<uint32_t>(a.blk_pos[1], t);
+            }
         }
-    }
-    int32_t l0 = 0;
-    if (RED == 0) {
-        // the block's incidence lists, copied with 16-byte loads from the aligned-down start
-        l0 = a.blk_lptr[vb] & ~7;
-        const uint32_t n16 = (uint32_t)(a.blk_lptr[vb + nvb] - l0 + 7) >> 3;
-        const uint4 *src = (const uint4 *)(a.blk_list + l0);
-        for (uint32_t i = tid; i < n16; i += nthr) s_dyn4[i] = src[i];
     }
     if (has) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            s_d[k * nvb + tid] = ldc<double>(a.d[k], gv0);
-            if (NQ > 1) s_u[k * nvb + tid] = ldc<double>(a.u[k], gv0);
-            if (NQ > 2) s_w[k * nvb + tid] = ldc<double>(a.w[k], gv0);
-            if (RED == 1) s_acc[k * nvb + tid] = 0.0;
+            s_d[k * S + tid] = ldc<double>(a.d[k], gv0);
+            if (NQ > 1) s_u[k * S + tid] = ldc<double>(a.u[k], gv0);
+            if (NQ > 2) s_w[k * S + tid] = ldc<double>(a.w[k], gv0);
+            if (RED == 1) s_acc[k * S + tid] = 0.0;
         }
     }
-    for (uint32_t i = tid + nthr; i < nvb; i += nthr) {
-        const uint32_t gv = (uint32_t)a.blk_verts[vb + i];
+    for (uint32_t i = tid + nthr; i < S; i += nthr) {
+        const int32_t gvs = bverts[i];
+        if (gvs < 0) continue;
+        const uint32_t gv = (uint32_t)gvs;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            s_d[k * nvb + i] = ldc<double>(a.d[k], gv);
-            if (NQ > 1) s_u[k * nvb + i] = ldc<double>(a.u[k], gv);
-            if (NQ > 2) s_w[k * nvb + i] = ldc<double>(a.w[k], gv);
-            if (RED == 1) s_acc[k * nvb + i] = 0.0;
+            s_d[k * S + i] = ldc<double>(a.d[k], gv);
+            if (NQ > 1) s_u[k * S + i] = ldc<double>(a.u[k], gv);
+            if (NQ > 2) s_w[k * S + i] = ldc<double>(a.w[k], gv);
+            if (RED == 1) s_acc[k * S + i] = 0.0;
         }
     }
     __syncthreads();
@@ -629,35 +631,43 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
             for (int c = 0; c < 4; ++c)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) {
-                    qd[c][k] = s_d[k * nvb + sl[r][c]];
-                    qu[c][k] = (NQ > 1) ? s_u[k * nvb + sl[r][c]] : 0.0;
-                    qw[c][k] = (NQ > 2) ? s_w[k * nvb + sl[r][c]] : 0.0;
+                    qd[c][k] = s_d[k * S + sl[r][c]];
+                    qu[c][k] = (NQ > 1) ? s_u[k * S + sl[r][c]] : 0.0;
+                    qw[c][k] = (NQ > 2) ? s_w[k * S + sl[r][c]] : 0.0;
                 }
             T h[12];
             const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
             if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
             if (RED == 0) {
+                const uint32_t p[4] = {pw[r][0] & 0xffffu, pw[r][0] >> 16, pw[r][1] & 0xffffu, pw[r][1] >> 16};
 #pragma unroll
-                for (int j = 0; j < 12; ++j) s_h[j * BT + tl] = h[j];
+                for (int c = 0; c < 4; ++c) {
+                    s_h[p[c]] = h[3 * c];
+                    s_h[LB + p[c]] = h[3 * c + 1];
+                    s_h[2 * LB + p[c]] = h[3 * c + 2];
+                }
             } else {
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) atomicAdd(&s_acc[k * nvb + sl[r][c]], (double)h[3 * c + k]);
+                    for (int k = 0; k < 3; ++k) atomicAdd(&s_acc[k * S + sl[r][c]], (double)h[3 * c + k]);
             }
         }
     }
     __syncthreads();
     if (RED == 0) {
-        if (has) reduce_slot<T>(a, s_list, s_h, BT, bsh, gv0, hp0, j00 - l0, j10 - l0);
-        for (uint32_t i = tid + nthr; i < nvb; i += nthr)
-            reduce_slot<T>(a, s_list, s_h, BT, bsh, (uint32_t)a.blk_verts[vb + i], a.blk_hpos[vb + i],
-                           a.blk_lptr[vb + i] - l0, a.blk_lptr[vb + i + 1] - l0);
+        if (has) reduce_slot<T>(a, s_h, LB, gv0, hp0, j00, j10);
+        for (uint32_t i = tid + nthr; i < S; i += nthr) {
+            const int32_t gvs = bverts[i];
+            if (gvs >= 0) reduce_slot<T>(a, s_h, LB, (uint32_t)gvs, bhpos[i], brow[i], brow[i + 1]);
+        }
     } else {
-        for (uint32_t i = tid; i < nvb; i += nthr) {
-            const uint32_t gv = i == tid ? gv0 : (uint32_t)a.blk_verts[vb + i];
-            const int32_t hp = i == tid ? hp0 : a.blk_hpos[vb + i];
-            double v0 = s_acc[i], v1 = s_acc[nvb + i], v2 = s_acc[2 * nvb + i];
+        for (uint32_t i = tid; i < S; i += nthr) {
+            const int32_t gvs = i == tid ? gvs0 : bverts[i];
+            if (gvs < 0) continue;
+            const uint32_t gv = (uint32_t)gvs;
+            const int32_t hp = i == tid ? hp0 : bhpos[i];
+            double v0 = s_acc[i], v1 = s_acc[S + i], v2 = s_acc[2 * S + i];
             if (hp < 0) {
                 if (a.accumulate) {
                     v0 += ldc<double>(a.out[0], gv);
@@ -677,7 +687,6 @@ __global__ __launch_bounds__(256) void k_block(ElemArgs a) {
     }
 }
 
-// Sum each shared vertex's halo entries (its blocks' partials, in block order).
 // OWNER strategy: workgroup = one block of owned vertices.  The block stages
 // the fields of its vertices (owned, then ghosts) in LDS, evaluates every tet
 // listed for it, writes the rows of owned corners to their positions in the
@@ -729,7 +738,7 @@ __global__ __launch_bounds__(256) void k_owner(ElemArgs a) {
         T b[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) b[k] = ldc<T>(a.B[k], t);
-        const T V0 = ldc<T>(a.V0, t);
+        const T V0 = tet_V0(b);
         T mu, lam;
         if (a.mu_t) {
             mu = ldc<T>(a.mu_t, t);
@@ -797,6 +806,7 @@ static void launch_owner(ElemOp op, const ElemArgs &a, unsigned grid, size_t shm
     HIPCHK(hipGetLastError());
 }
 
+// Sum each shared vertex's halo entries (its blocks' partials, in block order).
 __global__ __launch_bounds__(256) void k_halo_reduce(const double *halo, const int32_t *sh_vert, const int32_t *sh_ptr,
                                                      const int32_t *sh_pos, uint32_t S, double *o0, double *o1,
                                                      double *o2, int accumulate, const int *skip) {
@@ -929,10 +939,11 @@ static ElemArgs base_args(ebbx_fem_s *F) {
     a.lam = F->lam;
     a.n_inv = F->status.as<unsigned long long>();
     a.tmesh = F->tmesh;
-    a.blk_vptr = F->blk_vptr.as<int32_t>();
     a.blk_verts = F->blk_verts.as<int32_t>();
-    a.blk_lptr = F->blk_lptr.as<int32_t>();
-    a.blk_list = F->blk_list.as<uint16_t>();
+    a.blk_row = F->blk_lptr.as<uint16_t>();
+    a.blk_stride = (uint32_t)F->blk_maxv;
+    a.blk_pos[0] = F->blk_pos.as<uint32_t>();
+    a.blk_pos[1] = F->blk_pos.as<uint32_t>() + nt;
     a.blk_hpos = F->blk_hpos.as<int32_t>();
     a.slot[0] = F->blk_local.as<uint32_t>();
     a.slot[1] = F->blk_local.as<uint32_t>() + (F->blk_w == 2 ? nt : 0);
@@ -956,7 +967,15 @@ size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
     const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
     const size_t stage = (size_t)3 * nq * F->blk_maxv * sizeof(double);
     if (F->blk_red == 1) return stage + (size_t)3 * F->blk_maxv * sizeof(double);
-    return (size_t)8 * F->blk_tets + 16 + stage + (size_t)12 * F->blk_tets * F->esize;
+    return stage + (size_t)12 * F->blk_tets * F->esize;
+}
+
+// LDS a workgroup may allocate on the current device (160 KiB on gfx950).
+static size_t lds_limit() {
+    int dev = 0, v = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    return v > 0 ? (size_t)v : (size_t)64 * 1024;
 }
 
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
@@ -979,7 +998,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
     if (F->strategy == EBBX_STRAT_OWNER) {
         const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
         const size_t shmem = (size_t)3 * nq * F->own_maxv * sizeof(double) + (size_t)3 * F->own_maxinc * F->esize;
-        if (shmem > 64 * 1024)
+        if (shmem > lds_limit())
             fail(EBBX_E_STATE, "owner strategy needs %zu bytes of LDS per block; use fewer vertices per block",
                  shmem);
         const unsigned grid = (unsigned)F->own_nblk;
@@ -994,7 +1013,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
     }
     if (F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS) {
         const size_t shmem = block_shmem(F, op);
-        if (shmem > 64 * 1024)
+        if (shmem > lds_limit())
             fail(EBBX_E_STATE, "block strategy needs %zu bytes of LDS per block (%d vertices); reorder the mesh "
                  "(Morton) or use smaller blocks", shmem, F->blk_maxv);
         const int threads = std::min(F->blk_tets, 256), tpt = F->blk_tets / threads;
@@ -1129,7 +1148,7 @@ __global__ __launch_bounds__(256) void k_egrad(ElemArgs a, const double *E_tet, 
     T b[9];
 #pragma unroll
     for (int k = 0; k < 9; ++k) b[k] = ldc<T>(a.B[k], t);
-    const T V0 = ldc<T>(a.V0, t);
+    const T V0 = tet_V0(b);
     T mu, lam;
     if (a.mu_t) {
         mu = ldc<T>(a.mu_t, t);
@@ -1295,12 +1314,13 @@ int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hip
 // ---- block tables -----------------------------------------------------------------------
 
 // Tets are cut into blocks of bt consecutive rows.  Per block: the sorted set of
-// vertices it touches, each corner's slot in that set, each vertex's incidence
-// list inside the block (entries c * bt + local tet, ordered by local tet then
-// corner), and where its partial sum goes: nowhere else if the block holds
-// every incident tet of the vertex (the block stores it), otherwise a halo
-// position.  Halo positions are grouped by vertex, in block order; vertices
-// that no tet touches get an empty run, so the halo pass zeroes them.
+// vertices it touches, each corner's slot in that set, the block's incidences
+// ordered by (vertex, local tet, corner) with each corner's row in that order
+// and each vertex's run of rows, and where a vertex's sum goes: nowhere else if
+// the block holds every incident tet of the vertex (the block stores it),
+// otherwise a halo position.  Halo entries are block-major; the shared-vertex
+// table lists each vertex's entries in block order, and vertices that no tet
+// touches get an empty run, so the halo pass zeroes them.
 void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
     const int64_t nt = F->nt, nv = F->nv;
     if (bt != 64 && bt != 128 && bt != 256 && bt != 512 && bt != 1024)
@@ -1311,17 +1331,17 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
     std::vector<int64_t> rp((size_t)(nv + 1));
     HIPCHK(hipMemcpy(rp.data(), F->group->row_ptr.get(), rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
     std::vector<int32_t> vptr((size_t)nblk + 1, 0), verts, lptr(1, 0);
-    std::vector<uint16_t> list;
     std::vector<uint8_t> own;
-    std::vector<uint16_t> local((size_t)(4 * nt));
+    std::vector<uint16_t> local((size_t)(4 * nt)), rowpos((size_t)(4 * nt));
+    int64_t list_n = 0;   // incidence rows so far (all blocks)
     verts.reserve((size_t)(nt + 16));
     own.reserve((size_t)(nt + 16));
     lptr.reserve((size_t)(nt + 16));
-    list.reserve((size_t)(4 * nt));
     std::vector<std::pair<int32_t, int32_t>> buf;   // (vertex, local tet * 4 + corner)
     int32_t maxv = 1;
     for (int64_t b = 0; b < nblk; ++b) {
         const int64_t t0 = b * bt, t1 = std::min<int64_t>(nt, t0 + bt);
+        const int64_t list_b0 = list_n;
         buf.clear();
         for (int64_t t = t0; t < t1; ++t)
             for (int c = 0; c < 4; ++c) buf.push_back({keys[(size_t)(c * nt + t)], (int32_t)(4 * (t - t0) + c)});
@@ -1335,10 +1355,11 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
             for (size_t k = i; k < j; ++k) {
                 const int32_t tl = buf[k].second >> 2, c = buf[k].second & 3;
                 local[(size_t)(c * nt + t0 + tl)] = (uint16_t)nb;
-                list.push_back((uint16_t)(c * bt + tl));
+                rowpos[(size_t)(c * nt + t0 + tl)] = (uint16_t)(list_n - list_b0);   // row in the block
+                ++list_n;
             }
             verts.push_back(v);
-            lptr.push_back((int32_t)list.size());
+            lptr.push_back((int32_t)list_n);
             own.push_back((int64_t)(j - i) == rp[(size_t)v + 1] - rp[(size_t)v] ? 1 : 0);
             ++nb;
             i = j;
@@ -1348,9 +1369,13 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
         if (verts.size() >= (size_t)(1u << 31)) fail(EBBX_E_ARG, "block tables exceed int32");
     }
     if (maxv > 65535) fail(EBBX_E_ARG, "a block touches %d vertices (limit 65535)", maxv);
-    // the kernel copies each block's list with 16-byte loads from the aligned-down
-    // start, so the array carries 8 entries of tail padding that nothing references
-    for (int k = 0; k < 8; ++k) list.push_back(0);
+    if (list_n >= (int64_t(1) << 31)) fail(EBBX_E_ARG, "block tables exceed int32");
+    // per tet: the rows of its four corners in its block's incidence order
+    std::vector<uint32_t> pos((size_t)(2 * std::max<int64_t>(nt, 1)), 0u);
+    for (int64_t t = 0; t < nt; ++t) {
+        pos[(size_t)t] = (uint32_t)rowpos[(size_t)t] | ((uint32_t)rowpos[(size_t)(nt + t)] << 16);
+        pos[(size_t)(nt + t)] = (uint32_t)rowpos[(size_t)(2 * nt + t)] | ((uint32_t)rowpos[(size_t)(3 * nt + t)] << 16);
+    }
     // packed slots: 4 x 8 bits per word if every block has <= 256 vertices
     const int w = maxv <= 256 ? 1 : 2;
     std::vector<uint32_t> packed((size_t)(w * std::max<int64_t>(nt, 1)), 0u);
@@ -1399,11 +1424,30 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
         dst.reset(std::max<size_t>(bytes, 8), s);
         if (bytes) HIPCHK(hipMemcpy(dst.get(), src, bytes, hipMemcpyHostToDevice));
     };
+    // fixed-stride copies: block b's vertices at [b*maxv, (b+1)*maxv), padded with -1,
+    // and its block-relative row starts at [b*(maxv+1), (b+1)*(maxv+1))
+    const size_t S = (size_t)maxv;
+    std::vector<int32_t> pverts((size_t)nblk * S, -1), phpos((size_t)nblk * S, -1);
+    std::vector<uint16_t> prow((size_t)nblk * (S + 1), 0);
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int32_t a0 = vptr[(size_t)b], a1 = vptr[(size_t)b + 1];
+        const int32_t base = lptr[(size_t)a0], tot = lptr[(size_t)a1] - base;
+        for (size_t i = 0; i <= S; ++i) {
+            const int32_t k = a0 + (int32_t)i;
+            if (k < a1) {
+                pverts[(size_t)b * S + i] = verts[(size_t)k];
+                phpos[(size_t)b * S + i] = hpos[(size_t)k];
+                prow[(size_t)b * (S + 1) + i] = (uint16_t)(lptr[(size_t)k] - base);
+            } else {
+                prow[(size_t)b * (S + 1) + i] = (uint16_t)tot;
+            }
+        }
+    }
     up(F->blk_vptr, vptr.data(), vptr.size() * sizeof(int32_t));
-    up(F->blk_verts, verts.data(), verts.size() * sizeof(int32_t));
-    up(F->blk_lptr, lptr.data(), lptr.size() * sizeof(int32_t));
-    up(F->blk_list, list.data(), list.size() * sizeof(uint16_t));
-    up(F->blk_hpos, hpos.data(), hpos.size() * sizeof(int32_t));
+    up(F->blk_verts, pverts.data(), pverts.size() * sizeof(int32_t));
+    up(F->blk_lptr, prow.data(), prow.size() * sizeof(uint16_t));
+    up(F->blk_pos, pos.data(), pos.size() * sizeof(uint32_t));
+    up(F->blk_hpos, phpos.data(), phpos.size() * sizeof(int32_t));
     up(F->blk_local, packed.data(), packed.size() * sizeof(uint32_t));
     up(F->sh_vert, sh_vert.data(), sh_vert.size() * sizeof(int32_t));
     up(F->sh_ptr, sh_ptr.data(), sh_ptr.size() * sizeof(int32_t));

@@ -27,11 +27,12 @@ struct ElemArgs {
     unsigned long long *n_inv;  // inverted-element counters (one per mesh)
     const int32_t *tmesh;       // per-tet mesh ids selecting the counter, or NULL (one mesh)
     // block strategy
-    const int32_t *blk_vptr;    // (nblk + 1) offsets into blk_verts
-    const int32_t *blk_verts;   // global vertex ids per block, sorted
-    const int32_t *blk_lptr;    // per block vertex: [lptr[i], lptr[i+1]) in blk_list
-    const uint16_t *blk_list;   // incidences c*BT + local tet of each block vertex, fixed order
+    // block tables at a fixed stride of blk_stride vertices per block (padded with vertex -1)
+    const int32_t *blk_verts;   // global vertex ids of each block, sorted
+    const uint16_t *blk_row;    // per block, blk_stride + 1 entries: vertex i's rows are [row[i], row[i+1])
+    const uint32_t *blk_pos[2]; // per tet: rows of corners (0,1) and (2,3) within its block, 16 bits each
     const int32_t *blk_hpos;    // per block vertex: halo position, or -1 if the block owns it
+    uint32_t blk_stride;
     const uint32_t *slot[2];    // packed corner slots within the block (one or two words per tet)
     double *halo;               // partial sums of shared vertices, 3 per entry, block-major
     uint32_t nblk;              // tet blocks
@@ -117,7 +118,7 @@ struct ebbx_fem_s {
     int64_t blk_nverts = 0;    // entries of blk_verts over all blocks
     int64_t sh_n = 0;          // vertices summed from the halo (shared or untouched)
     int64_t halo_n = 0;        // halo entries
-    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_list, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos;
+    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_pos, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos;
     bool blocks_built = false;
     // owner strategy tables
     int32_t own_vb = 0;        // owned vertices per block

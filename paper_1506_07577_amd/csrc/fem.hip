@@ -50,10 +50,13 @@ void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s)
     if (strategy == EBBX_STRAT_OWNER) {
         int32_t vb = block ? block : (F->prec == EBBX_F32 ? 128 : 64);
         if (F->own_vb != vb) build_owner(F, vb, s);
-        // default size: fall back to 64 owned vertices when the stiffness product's
-        // LDS (staged d and u, and the owned rows) would exceed 64 KiB
-        const size_t kmul_lds = (size_t)6 * F->own_maxv * sizeof(double) + (size_t)3 * F->own_maxinc * F->esize;
-        if (!block && vb > 64 && kmul_lds > 64 * 1024) {
+        // default size: fall back to 64 owned vertices when the T-product's LDS
+        // (staged d, a and w, and the owned rows) would exceed what a workgroup may hold
+        const size_t tmul_lds = (size_t)9 * F->own_maxv * sizeof(double) + (size_t)3 * F->own_maxinc * F->esize;
+        int dev = 0, lim = 0;
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        if (!block && vb > 64 && tmul_lds > (size_t)std::max(lim, 64 * 1024)) {
             vb = 64;
             build_owner(F, vb, s);
         }
