@@ -311,6 +311,16 @@ ebbx_status ebbx_fem_Tmul(ebbx_fem fem, const double *d, const double *a, const 
 ebbx_status ebbx_fem_E_grad(ebbx_fem fem, const double *d, const double *v, const double *w, double dt,
                             double *E_bar, ebbx_stream stream);
 
+/* Vector-Jacobian products of the element maps; every output accumulates and
+ * is nullable.  forces (f = f(d)):  d_bar += K(d) w,  E_bar[t] += w_t . f_t / E_t.
+ * Kmul (y = K(d) u):  d_bar += T[u, w],  u_bar += K(d) w,  E_bar[t] += w_t . K_t u / E_t
+ * (K is symmetric; f and K are linear in E_t at fixed nu).  FP64 (3, nv)
+ * vectors, E_bar FP64 (nt).  EBBX_E_PHASE if an output aliases an input. */
+ebbx_status ebbx_fem_forces_vjp(ebbx_fem fem, const double *d, const double *w, double *d_bar, double *E_bar,
+                                ebbx_stream stream);
+ebbx_status ebbx_fem_Kmul_vjp(ebbx_fem fem, const double *d, const double *u, const double *w, double *d_bar,
+                              double *u_bar, double *E_bar, ebbx_stream stream);
+
 /* Replace the material: per-tet E_tet_dev (nt FP64, borrowed and kept as the
  * E_t of ebbx_fem_E_grad) or uniform E; per-tet nu_tet_dev (nt FP64) or
  * uniform nu.  Enqueued on stream. */

@@ -1141,7 +1141,8 @@ void elem_energy(ebbx_fem_s *F, const double *d, double *out_dev, hipStream_t s)
 // E at fixed nu, so d(f_t)/dE_t = f_t / E_t and d(K_t)/dE_t = K_t / E_t:
 //   E_bar[t] += w_t . (dt f_t + dt^2 K_t v) / E_t.
 template <class T, int MODEL>
-__global__ __launch_bounds__(256) void k_egrad(ElemArgs a, const double *E_tet, double E, double dt, double *E_bar) {
+__global__ __launch_bounds__(256) void k_egrad(ElemArgs a, const double *E_tet, double E, double cf, double ck,
+                                               double *E_bar) {
     const uint32_t nt = a.nt;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
@@ -1160,33 +1161,39 @@ __global__ __launch_bounds__(256) void k_egrad(ElemArgs a, const double *E_tet, 
     uint32_t v[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) v[c] = (uint32_t)ldc<int32_t>(a.key[c], t);
+    const bool with_k = ck != 0.0;   // uniform: the stiffness term (and its direction) is optional
     double qd[4][3], qv[4][3];
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             qd[c][k] = ldc<double>(a.d[k], v[c]);
-            qv[c][k] = ldc<double>(a.u[k], v[c]);
+            qv[c][k] = with_k ? ldc<double>(a.u[k], v[c]) : 0.0;
         }
     T G[9], dF[9], P[9], dP[9], hf[12], hk[12];
     grad_from(qd, b, G);
-    grad_from(qv, b, dF);
     stress_scaled<T, MODEL>(mu, lam, V0, G, P);
-    dstress_scaled<T, MODEL>(mu, lam, V0, G, dF, dP);
     corner_out(P, b, hf);
-    corner_out(dP, b, hk);
+    if (with_k) {
+        grad_from(qv, b, dF);
+        dstress_scaled<T, MODEL>(mu, lam, V0, G, dF, dP);
+        corner_out(dP, b, hk);
+    } else {
+#pragma unroll
+        for (int j = 0; j < 12; ++j) hk[j] = (T)0;
+    }
     double acc = 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            acc += ldc<double>(a.w[k], v[c]) * (dt * (double)hf[3 * c + k] + dt * dt * (double)hk[3 * c + k]);
+            acc += ldc<double>(a.w[k], v[c]) * (cf * (double)hf[3 * c + k] + ck * (double)hk[3 * c + k]);
     const double Et = E_tet ? E_tet[t] : E;
     E_bar[t] += acc / Et;
 }
 
-void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double dt, double *E_bar,
-                hipStream_t s) {
+void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double cf, double ck,
+                double *E_bar, hipStream_t s) {
     if (F->nt == 0) return;
     ElemArgs a = base_args(F);
     set_vec(a.d, d, (uint32_t)F->nv);
@@ -1195,11 +1202,11 @@ void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w
     const unsigned g = grid_n(F->nt, 256, 1ll << 31);
     const double *Et = F->per_tet ? F->E_tet : nullptr;
     if (F->prec == EBBX_F32) {
-        if (F->model == EBBX_STVK) hipLaunchKernelGGL((k_egrad<float, EBBX_STVK>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
-        else hipLaunchKernelGGL((k_egrad<float, EBBX_NH>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
+        if (F->model == EBBX_STVK) hipLaunchKernelGGL((k_egrad<float, EBBX_STVK>), dim3(g), dim3(256), 0, s, a, Et, F->E, cf, ck, E_bar);
+        else hipLaunchKernelGGL((k_egrad<float, EBBX_NH>), dim3(g), dim3(256), 0, s, a, Et, F->E, cf, ck, E_bar);
     } else {
-        if (F->model == EBBX_STVK) hipLaunchKernelGGL((k_egrad<double, EBBX_STVK>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
-        else hipLaunchKernelGGL((k_egrad<double, EBBX_NH>), dim3(g), dim3(256), 0, s, a, Et, F->E, dt, E_bar);
+        if (F->model == EBBX_STVK) hipLaunchKernelGGL((k_egrad<double, EBBX_STVK>), dim3(g), dim3(256), 0, s, a, Et, F->E, cf, ck, E_bar);
+        else hipLaunchKernelGGL((k_egrad<double, EBBX_NH>), dim3(g), dim3(256), 0, s, a, Et, F->E, cf, ck, E_bar);
     }
     HIPCHK(hipGetLastError());
 }

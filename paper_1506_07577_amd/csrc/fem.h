@@ -55,9 +55,9 @@ struct ElemArgs {
 // the raw stiffness diagonal K[(v,c),(v,c)].
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
                  hipStream_t s, const int *skip = nullptr, const double *w = nullptr, const int *mdone = nullptr);
-// E_bar[t] += w_t . (dt f_t + dt^2 K_t v) / E_t over the tets (no scatter).
-void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double dt, double *E_bar,
-                hipStream_t s);
+// E_bar[t] += w_t . (cf f_t(d) + ck K_t(d) v) / E_t over the tets (no scatter; v unused if ck = 0).
+void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double cf, double ck,
+                double *E_bar, hipStream_t s);
 // Recompute the per-tet Lame parameters from per-tet (or uniform) E and nu.
 void elem_set_material(ebbx_fem_s *F, const double *E_tet, const double *nu_tet, double E, double nu, hipStream_t s);
 // Total energy into out_dev[0].

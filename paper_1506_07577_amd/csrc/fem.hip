@@ -277,7 +277,39 @@ extern "C" ebbx_status ebbx_fem_E_grad(ebbx_fem fem, const double *d, const doub
     auto *F = check_fem(fem);
     if ((!d || !v || !w) && F->nv > 0) fail(EBBX_E_ARG, "a vector argument is NULL");
     if (!E_bar && F->nt > 0) fail(EBBX_E_ARG, "E_bar is NULL");
-    elem_egrad(F, d, v, w, dt, E_bar, (hipStream_t)stream);
+    elem_egrad(F, d, v, w, dt, dt * dt, E_bar, (hipStream_t)stream);
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_fem_forces_vjp(ebbx_fem fem, const double *d, const double *w, double *d_bar,
+                                           double *E_bar, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    if ((!d || !w) && F->nv > 0) fail(EBBX_E_ARG, "d or w is NULL");
+    const size_t bytes = (size_t)(3 * F->nv) * sizeof(double);
+    if (d_bar && F->nv > 0 && (overlap(d_bar, d, bytes) || overlap(d_bar, w, bytes)))
+        fail(EBBX_E_PHASE, "d_bar aliases d or w");
+    hipStream_t s = (hipStream_t)stream;
+    if (d_bar) elem_launch(F, OP_KMUL, d, w, d_bar, 1, s);          // (df/dd)^T w = K w (K symmetric)
+    if (E_bar) elem_egrad(F, d, nullptr, w, 1.0, 0.0, E_bar, s);    // w_t . f_t / E_t
+    EBBX_API_END
+}
+
+extern "C" ebbx_status ebbx_fem_Kmul_vjp(ebbx_fem fem, const double *d, const double *u, const double *w,
+                                         double *d_bar, double *u_bar, double *E_bar, ebbx_stream stream) {
+    EBBX_API_BEGIN
+    auto *F = check_fem(fem);
+    if ((!d || !u || !w) && F->nv > 0) fail(EBBX_E_ARG, "d, u or w is NULL");
+    const size_t bytes = (size_t)(3 * F->nv) * sizeof(double);
+    if (F->nv > 0)
+        for (const void *o : {(const void *)d_bar, (const void *)u_bar})
+            if (o && (overlap(o, d, bytes) || overlap(o, u, bytes) || overlap(o, w, bytes)))
+                fail(EBBX_E_PHASE, "an output aliases d, u or w");
+    if (d_bar && u_bar && F->nv > 0 && overlap(d_bar, u_bar, bytes)) fail(EBBX_E_PHASE, "d_bar aliases u_bar");
+    hipStream_t s = (hipStream_t)stream;
+    if (d_bar) elem_launch(F, OP_TMUL, d, u, d_bar, 1, s, nullptr, w);   // grad_d (w . K(d) u) = T[u, w]
+    if (u_bar) elem_launch(F, OP_KMUL, d, w, u_bar, 1, s);               // K^T w = K w
+    if (E_bar) elem_egrad(F, d, u, w, 0.0, 1.0, E_bar, s);                // w_t . K_t u / E_t
     EBBX_API_END
 }
 

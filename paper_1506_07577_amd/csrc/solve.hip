@@ -620,7 +620,7 @@ extern "C" ebbx_status ebbx_implicit_step_vjp(ebbx_fem fem, const double *d_n, c
     hipLaunchKernelGGL(k_vjp_end, dim3(S.nch), dim3(VT), 0, s, S.w, gx, p.dt, nv,
                        (const CGState *)S.state.as<CGState>(), S.ch, p.tol, d_bar, v_bar, stats_dev);
     HIPCHK(hipGetLastError());
-    if (E_bar) elem_egrad(F, S.w.dn, v_np1, S.w.x, p.dt, E_bar, s);
+    if (E_bar) elem_egrad(F, S.w.dn, v_np1, S.w.x, p.dt, p.dt * p.dt, E_bar, s);
     EBBX_API_END
 }
 

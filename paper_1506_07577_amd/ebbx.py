@@ -114,6 +114,8 @@ def lib():
         "ebbx_fem_Tmul": ([P, P, P, P, P, I32_, P], I32_),
         "ebbx_fem_E_grad": ([P, P, P, P, D, P, P], I32_),
         "ebbx_fem_set_material": ([P, P, P, D, D, P], I32_),
+        "ebbx_fem_forces_vjp": ([P, P, P, P, P, P], I32_),
+        "ebbx_fem_Kmul_vjp": ([P, P, P, P, P, P, P, P], I32_),
         "ebbx_implicit_step_vjp": ([P, P, P, C.POINTER(StepParams), P, P, P, P, P, P, P], I32_),
         "ebbx_fem_autotune": ([P, P, P, S, C.POINTER(TuneEntry), I32_, C.POINTER(I32_), P], I32_),
         "ebbx_batch_create": ([P, P, P, C.POINTER(BatchFields), C.POINTER(FemParams), C.POINTER(P)], I32_),
@@ -354,6 +356,30 @@ class Fem:
         _check(lib().ebbx_fem_E_grad(self.h, _ptr(d), _ptr(v), _ptr(w), float(dt), _ptr(E_bar),
                                      _stream(stream)))
         return E_bar
+
+    def forces_vjp(self, d, w, d_bar=None, E_bar=None, stream=None):
+        """d_bar += K(d) w; E_bar += per-tet w.f_t/E_t (outputs accumulate, nullable)."""
+        self._vec(d, "d")
+        self._vec(w, "w")
+        if d_bar is not None:
+            self._vec(d_bar, "d_bar")
+        if E_bar is not None:
+            _dev(E_bar, torch.float64, "E_bar")
+        _check(lib().ebbx_fem_forces_vjp(self.h, _ptr(d), _ptr(w), _ptr(d_bar), _ptr(E_bar), _stream(stream)))
+        return d_bar, E_bar
+
+    def kmul_vjp(self, d, u, w, d_bar=None, u_bar=None, E_bar=None, stream=None):
+        """d_bar += T[u, w]; u_bar += K(d) w; E_bar += per-tet w.K_t u/E_t (accumulate, nullable)."""
+        for t, n in ((d, "d"), (u, "u"), (w, "w")):
+            self._vec(t, n)
+        for t, n in ((d_bar, "d_bar"), (u_bar, "u_bar")):
+            if t is not None:
+                self._vec(t, n)
+        if E_bar is not None:
+            _dev(E_bar, torch.float64, "E_bar")
+        _check(lib().ebbx_fem_Kmul_vjp(self.h, _ptr(d), _ptr(u), _ptr(w), _ptr(d_bar), _ptr(u_bar), _ptr(E_bar),
+                                       _stream(stream)))
+        return d_bar, u_bar, E_bar
 
     def set_material(self, E_tet=None, nu_tet=None, E=0.0, nu=0.3, stream=None):
         """Per-tet (nt,) FP64 CUDA tensors or uniform values.  The tensors are borrowed."""

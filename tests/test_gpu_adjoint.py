@@ -320,3 +320,48 @@ def test_step_vjp_full_size_vs_oracle():
     assert nerr(_host(db), db_e) < 1e-9
     assert nerr(_host(vb), vb_e) < 1e-9
     assert nerr(E_bar.cpu().numpy(), Eb_e) < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# vector-Jacobian products of the element maps
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("strategy", ["atomic", "block", "owner"])
+@pytest.mark.parametrize("mname,model", MODELS)
+def test_forces_and_kmul_vjp(mname, model, strategy):
+    m = mg.jitter(mg.kuhn_cube(2), 0.01, seed=0)
+    E_tet, _, _ = mg.adjoint_recipe(m, seed=2)
+    mesh, ref = _pair(m, model, E_tet, strategy=strategy)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    u = mg.direction(m, 11)
+    w = mg.direction(m, 12)
+    fem = mesh.fem
+    # forces: d_bar += K w (onto ones: accumulation), E_bar per tet from one-tet oracle FEMs
+    d_bar = _dev(np.ones_like(d))
+    E_bar = torch.full((m.nt,), 2.0, dtype=torch.float64, device="cuda")
+    fem.forces_vjp(_dev(d), _dev(w), d_bar=d_bar, E_bar=E_bar)
+    assert nerr(_host(d_bar) - 1.0, ref.kmul(d, w)) < 1e-10
+    expf = np.zeros(m.nt)
+    expk = np.zeros(m.nt)
+    for t in range(m.nt):
+        one = oracle.FEM.create(model, m.X, m.tets[t:t + 1], E_tet[t], 0.3)
+        expf[t] = np.sum(w * one.forces(d)) / E_tet[t]
+        expk[t] = np.sum(w * one.kmul(d, u)) / E_tet[t]
+    assert nerr(E_bar.cpu().numpy() - 2.0, expf) < 1e-10
+    # Kmul: d_bar += T[u, w], u_bar += K w, E_bar += w.K_t u / E_t
+    d_bar = torch.zeros_like(d_bar)
+    u_bar = torch.zeros_like(d_bar)
+    E_bar = torch.zeros(m.nt, dtype=torch.float64, device="cuda")
+    fem.kmul_vjp(_dev(d), _dev(u), _dev(w), d_bar=d_bar, u_bar=u_bar, E_bar=E_bar)
+    assert nerr(_host(d_bar), ref.tmul(d, u, w)) < 1e-10
+    assert nerr(_host(u_bar), ref.kmul(d, w)) < 1e-10
+    assert nerr(E_bar.cpu().numpy(), expk) < 1e-10
+    # the E-gradients sum to the full contraction (linearity in E)
+    assert abs(float((E_bar.cpu() * torch.as_tensor(E_tet)).sum()) - float(np.sum(w * ref.kmul(d, u)))) <= \
+        1e-10 * np.abs(w * ref.kmul(d, u)).sum()
+    # nullable outputs and aliasing
+    fem.kmul_vjp(_dev(d), _dev(u), _dev(w))
+    z = _dev(d)
+    with pytest.raises(ebbx.EbbxError) as e:
+        fem.kmul_vjp(z, _dev(u), _dev(w), d_bar=z)
+    assert e.value.code == ebbx.E_PHASE

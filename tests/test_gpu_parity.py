@@ -364,3 +364,30 @@ def test_plain_workload_step_residual():
     assert r <= max(10 * s.rel_res, 1e-5)
     assert np.all(dv[m.pinned == 1] == 0)
     mesh.fem.close()
+
+
+@pytest.mark.parametrize("order", ["scrambled", "morton"])
+def test_locality_workload_full_size(order):
+    """128^3 cube (12,582,912 tets), StVK FP64, vertex ids and tet rows scrambled (seed 1), then
+    the same mesh Morton-reordered: forces and K u of every strategy against the oracle over the
+    whole mesh (1e-10), and the deterministic strategies bitwise equal to each other."""
+    w = mg.workload_locality(128)
+    m = w.mesh
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    u = mg.direction(m, 11)
+    ref = oracle.FEM.create(w.model, m.X, m.tets, w.E, w.nu, pinned=m.pinned)
+    ef, ek = ref.forces(d), ref.kmul(d, u)
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=w.model, elem_prec=_prec(w.prec), E=w.E, nu=w.nu,
+                        strategy=ebbx.STRAT_SEG, morton=(order == "morton"))
+    dd, ud = mesh.to_dev(d), mesh.to_dev(u)
+    seg_f, seg_k = mesh.fem.forces(dd).clone(), mesh.fem.kmul(dd, ud).clone()
+    assert nerr(mesh.from_dev(seg_f), ef) <= 1e-10
+    assert nerr(mesh.from_dev(seg_k), ek) <= 1e-10
+    for st in ["atomic", "block", "owner"]:
+        mesh.fem.set_strategy(_strat(st), 64 if st == "owner" else 0)
+        f, k = mesh.fem.forces(dd), mesh.fem.kmul(dd, ud)
+        assert nerr(mesh.from_dev(f), ef) <= 1e-10, st
+        assert nerr(mesh.from_dev(k), ek) <= 1e-10, st
+        if st == "owner":
+            assert torch.equal(f, seg_f) and torch.equal(k, seg_k)
+    mesh.fem.close()
