@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--all-strategies", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 256 MiB device-to-device copy first (counter calibration)")
+    ap.add_argument("--workload", default="plain", choices=["plain", "locality"],
+                    help="plain: the headline 64^3 line; locality: the 128^3 StVK FP64 mesh, scrambled "
+                         "then Morton-ordered, every strategy (a separate JSON line)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-step section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint section")
     return ap.parse_args()
@@ -177,6 +180,54 @@ def bench_adjoint(stream, plain_rate):
                     "segment recompute + 20 step VJPs (adjoint CG, K w, T[v, w], dL/dE)"}
 
 
+def bench_locality(args):
+    """Cold force and K u calls on the 128^3 StVK FP64 mesh (12,582,912 tets) with scrambled
+    vertex and tet order, then Morton order, under every scatter strategy."""
+    import torch
+
+    from paper_1506_07577_amd import ebbx
+    from paper_1506_07577_amd import meshgen as mg
+    w = mg.workload_locality(args.n if args.n != 64 else 128)
+    m = w.mesh
+    stream = torch.cuda.current_stream()
+    strat = {"atomic": (ebbx.STRAT_ATOMIC, 0), "seg": (ebbx.STRAT_SEG, 0), "block": (ebbx.STRAT_BLOCK, 0),
+             "owner": (ebbx.STRAT_OWNER, 64)}
+    rows = {}
+    for order in ("scrambled", "morton"):
+        mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=w.model, elem_prec=ebbx.F64, E=w.E, nu=w.nu,
+                            strategy=ebbx.STRAT_SEG, morton=(order == "morton"))
+        d = mesh.to_dev(mg.perturbed_state(m, 0.02, seed=10))
+        u = mesh.to_dev(mg.direction(m, 11))
+        f = torch.empty_like(d)
+        y = torch.empty_like(d)
+        for name, (sid, blk) in strat.items():
+            mesh.fem.set_strategy(sid, blk)
+            tf = time_events(lambda: (ebbx.cache_flush(1 << 30, stream), mesh.fem.forces(d, f, stream=stream)),
+                             stream, 1)   # warm-up
+            tf, tk = [], []
+            for _ in range(args.steps):
+                ebbx.cache_flush(1 << 30, stream)
+                tf += time_events(lambda: mesh.fem.forces(d, f, stream=stream), stream, 1)
+                ebbx.cache_flush(1 << 30, stream)
+                tk += time_events(lambda: mesh.fem.kmul(d, u, y, stream=stream), stream, 1)
+            bk = canonical_bytes(mesh.nt, mesh.nv, "kmul", 8)
+            tk_ms = statistics.mean(tk)
+            rows[f"{order}/{name}"] = {"force_us": round(1e3 * statistics.mean(tf), 1),
+                                       "kmul_us": round(1e3 * tk_ms, 1),
+                                       "kmul_GBps": round(bk / (tk_ms * 1e-3) / 1e9, 1),
+                                       "kmul_frac": round(bk / (tk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            log(f"{order}/{name}: {rows[f'{order}/{name}']}")
+        mesh.fem.close()
+        del mesh, d, u, f, y
+        torch.cuda.empty_cache()
+    out = {"metric": "tet force+Kmul cold call time by scatter strategy and vertex order", "unit": "us",
+           "workload": f"{m.n}^3 Kuhn cube, StVK FP64, E=1e5 nu=0.3, {m.nt} tets, {m.nv} verts",
+           "protocol": "1 GiB read-only cache flush before each call; HIP events on the launch stream; "
+                       f"mean of {args.steps} calls",
+           "algorithmic_bytes_kmul": canonical_bytes(m.nt, m.nv, "kmul", 8), "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -184,6 +235,13 @@ def main():
               "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.workload == "locality":
+        from paper_1506_07577_amd import ebbx
+        if not os.path.exists(ebbx.LIB_PATH):
+            raise SystemExit(f"{ebbx.LIB_PATH} is missing: run __graft_entry__.build() first")
+        torch.cuda.set_device(0)
+        bench_locality(args)
+        return
 
     from paper_1506_07577_amd import ebbx
     from paper_1506_07577_amd import meshgen as mg
