@@ -372,7 +372,7 @@ struct ebbx_fem_s::Step {
     hipGraphExec_t pre[2] = {nullptr, nullptr}, chunk = nullptr;
     hipGraph_t g_pre[2] = {nullptr, nullptr}, g_chunk = nullptr;
     hipStream_t cap = nullptr;
-    int chunk_iters = 0;
+    int first_iters = 0, chunk_iters = 0;
     bool valid = false;   // graphs match the parameters below
     // parameters baked into the graphs
     double dt = -1, g[3] = {0, 0, 0}, tol = -1;
@@ -445,11 +445,16 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
                        p.dt, p.g[0], p.g[1], p.g[2], p.precond, mode, S.ch, part);
     hipLaunchKernelGGL(k_step_init, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch,
                        (const unsigned long long *)n_inv, ctl);
-    // a chunk of CG iterations; every kernel is predicated on its mesh's done
-    // flag, the element map on the solve-wide all_done flag
-    S.chunk_iters = std::max(1, std::min(p.maxit, 128));
-    auto iterations = [&]() {
-        for (int it = 0; it < S.chunk_iters && it < p.maxit; ++it) {
+    // chunks of CG iterations; every kernel is predicated on its mesh's done flag,
+    // the element map on the solve-wide all_done flag.  A fixed-count solve
+    // (tol = 0) runs chunks of up to 128 without host checks.  With a tolerance
+    // the first chunk has 32 iterations and later ones 16, each launched only
+    // after the host has read that some mesh is still iterating: iterations
+    // past convergence cost a launch each, so the chunks stay short.
+    S.first_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 32 : 128));
+    S.chunk_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 16 : 128));
+    auto iterations = [&](int count) {
+        for (int it = 0; it < count && it < p.maxit; ++it) {
             elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &ctl->all_done, nullptr,
                         nm > 1 ? (const int *)(ctl + 1) : nullptr);
             hipLaunchKernelGGL(k_cg_Ap, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
@@ -463,12 +468,12 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     };
     // the preamble graph also holds the first chunk, so a solve that converges
     // within it is one graph launch
-    iterations();
+    iterations(S.first_iters);
     HIPCHK(hipGetLastError());
     S.pre[mode] = capture_end(cs, &S.g_pre[mode]);
-    if (!S.chunk && p.maxit > S.chunk_iters) {
+    if (!S.chunk && p.maxit > S.first_iters) {
         capture_begin(cs);
-        iterations();
+        iterations(S.chunk_iters);
         HIPCHK(hipGetLastError());
         S.chunk = capture_end(cs, &S.g_chunk);
     }
@@ -541,9 +546,8 @@ void run_solve(ebbx_fem_s *F, const ebbx_step_params &p, int mode, hipStream_t s
     auto &S = *F->step;
     // preamble + first chunk, then further chunks until maxit
     HIPCHK(hipGraphLaunch(S.pre[mode], s));
-    const int nchunks = p.maxit > 0 ? (p.maxit + S.chunk_iters - 1) / S.chunk_iters : 0;
     SolveCtl *ctl = S.ctl.as<SolveCtl>();
-    for (int c = 1; c < nchunks; ++c) {
+    for (int done = S.first_iters; done < p.maxit; done += S.chunk_iters) {
         // with a tolerance, stop launching once every mesh has finished
         if (p.tol > 0.0) {
             HIPCHK(hipMemcpyAsync(S.h_done, &ctl->all_done, sizeof(int), hipMemcpyDeviceToHost, s));
