@@ -168,7 +168,7 @@ enum { EBBX_STVK = 0, EBBX_NH = 1 };
  *   AUTO:      BLOCK with 256 tets per block (ebbx_fem_autotune times the
  *              alternatives on the domain itself).
  * The `block` argument of the calls below is the workgroup size (threads) for
- * ATOMIC and SEG, the number of tets per block (64..512, a power of two)
+ * ATOMIC and SEG, the number of tets per block (64..1024, a power of two)
  * for BLOCK and BLOCK_LDS, and the owned vertices per block (64, 128 or
  * 256) for OWNER; 0 picks the default. */
 enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3,

@@ -536,7 +536,7 @@ __device__ __forceinline__ void reduce_slot(const ElemArgs &a, const T *s_h, uin
 }
 
 template <class T, int MODEL, int OP, int TPT, int W, int RED>
-__global__ __launch_bounds__(256) void k_block(ElemArgs a) {
+__global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     extern __shared__ uint4 s_dyn4[];
     if (a.skip && *a.skip) return;   // uniform over the grid
     const uint32_t nt = a.nt;
@@ -832,6 +832,42 @@ __global__ __launch_bounds__(256) void k_halo_reduce(const double *halo, const i
     }
 }
 
+// The same sum with each shared vertex's halo positions in one fixed-width row
+// (NC x 4 entries, -1 padded, in block order): one dependent load fewer.
+template <int NC>
+__global__ __launch_bounds__(256) void k_halo_tab(const double *halo, const int32_t *sh_vert, const int4 *tab,
+                                                  uint32_t S, double *o0, double *o1, double *o2, int accumulate,
+                                                  const int *skip) {
+    if (skip && *skip) return;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)sh_vert[s];
+        int4 q[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) q[c] = tab[(size_t)s * NC + c];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int32_t p[4] = {q[c].x, q[c].y, q[c].z, q[c].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (p[k] >= 0) {
+                    const double *hq = halo + 3 * (size_t)p[k];
+                    a0 += hq[0];
+                    a1 += hq[1];
+                    a2 += hq[2];
+                }
+        }
+        if (accumulate) {
+            a0 += ldc<double>(o0, v);
+            a1 += ldc<double>(o1, v);
+            a2 += ldc<double>(o2, v);
+        }
+        stc<double>(o0, v, a0);
+        stc<double>(o1, v, a1);
+        stc<double>(o2, v, a2);
+    }
+}
+
 // Vertex-owned reduction of per-corner partials over the grouping (CSR rows in
 // increasing (tet, corner) order: a fixed summation order, so the result is
 // bitwise reproducible).
@@ -1016,8 +1052,8 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
         if (shmem > lds_limit())
             fail(EBBX_E_STATE, "block strategy needs %zu bytes of LDS per block (%d vertices); reorder the mesh "
                  "(Morton) or use smaller blocks", shmem, F->blk_maxv);
-        const int threads = std::min(F->blk_tets, 256), tpt = F->blk_tets / threads;
-        if (tpt > 2) fail(EBBX_E_ARG, "block strategy: at most 512 tets per block");
+        const int threads = std::min(F->blk_tets, 512), tpt = F->blk_tets / threads;
+        if (tpt > 2) fail(EBBX_E_ARG, "block strategy: at most 1024 tets per block");
         const unsigned grid = (unsigned)F->nblk;
         if (F->prec == EBBX_F32) {
             if (F->model == EBBX_STVK) launch_model<float, EBBX_STVK>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
@@ -1027,10 +1063,20 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
             else launch_model<double, EBBX_NH>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
         }
         if (F->sh_n > 0) {
-            hipLaunchKernelGGL(k_halo_reduce, dim3(grid_n(F->sh_n, 256, 1ll << 20)), dim3(256), 0, s,
-                               (const double *)F->halo.get(), F->sh_vert.as<int32_t>(), F->sh_ptr.as<int32_t>(),
-                               F->sh_pos.as<int32_t>(), (uint32_t)F->sh_n,
-                               out, out + nv, out + 2 * nv, accumulate, skip);
+            const dim3 g(grid_n(F->sh_n, 256, 1ll << 20));
+            const double *hl = (const double *)F->halo.get();
+            const int32_t *sv = F->sh_vert.as<int32_t>();
+            const int4 *tb = F->sh_tab.as<int4>();
+            const uint32_t sn = (uint32_t)F->sh_n;
+            switch (F->sh_nc) {
+            case 1: hipLaunchKernelGGL(k_halo_tab<1>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+            case 2: hipLaunchKernelGGL(k_halo_tab<2>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+            case 3: hipLaunchKernelGGL(k_halo_tab<3>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+            case 4: hipLaunchKernelGGL(k_halo_tab<4>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+            default:
+                hipLaunchKernelGGL(k_halo_reduce, g, dim3(256), 0, s, hl, sv, F->sh_ptr.as<int32_t>(),
+                                   F->sh_pos.as<int32_t>(), sn, out, out + nv, out + 2 * nv, accumulate, skip);
+            }
             HIPCHK(hipGetLastError());
         }
         return;
@@ -1459,6 +1505,17 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
     up(F->sh_vert, sh_vert.data(), sh_vert.size() * sizeof(int32_t));
     up(F->sh_ptr, sh_ptr.data(), sh_ptr.size() * sizeof(int32_t));
     up(F->sh_pos, sh_pos.data(), sh_pos.size() * sizeof(int32_t));
+    // fixed-width rows of halo positions when no vertex has more than 16 entries
+    int32_t maxm = 0;
+    for (size_t r = 0; r + 1 < sh_ptr.size(); ++r) maxm = std::max(maxm, sh_ptr[r + 1] - sh_ptr[r]);
+    F->sh_nc = maxm <= 16 ? std::max(1, (maxm + 3) / 4) : 0;
+    if (F->sh_nc > 0) {
+        const size_t w = (size_t)4 * F->sh_nc;
+        std::vector<int32_t> tab(std::max<size_t>(sh_vert.size() * w, 4), -1);
+        for (size_t r = 0; r < sh_vert.size(); ++r)
+            for (int32_t j = sh_ptr[r]; j < sh_ptr[r + 1]; ++j) tab[r * w + (size_t)(j - sh_ptr[r])] = sh_pos[(size_t)j];
+        up(F->sh_tab, tab.data(), tab.size() * sizeof(int32_t));
+    }
     F->halo.reset(std::max<size_t>((size_t)F->halo_n * 3 * sizeof(double), 8), s);
     F->blocks_built = true;
 }

@@ -118,7 +118,8 @@ struct ebbx_fem_s {
     int64_t blk_nverts = 0;    // entries of blk_verts over all blocks
     int64_t sh_n = 0;          // vertices summed from the halo (shared or untouched)
     int64_t halo_n = 0;        // halo entries
-    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_pos, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos;
+    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_pos, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos, sh_tab;
+    int32_t sh_nc = 0;         // int4 chunks per row of sh_tab (0: use the CSR form)
     bool blocks_built = false;
     // owner strategy tables
     int32_t own_vb = 0;        // owned vertices per block

@@ -66,7 +66,7 @@ void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s)
     }
     if (strategy == EBBX_STRAT_BLOCK || strategy == EBBX_STRAT_BLOCK_LDS) {
         const int32_t bt = block ? block : 256;
-        if (bt > 512) fail(EBBX_E_ARG, "block strategies take at most 512 tets per block");
+        if (bt > 1024) fail(EBBX_E_ARG, "block strategies take at most 1024 tets per block");
         if (!F->blocks_built || F->blk_tets != bt) build_blocks(F, bt, s);
         F->strategy = strategy;
         F->blk_red = strategy == EBBX_STRAT_BLOCK_LDS ? 1 : 0;
