@@ -1015,7 +1015,7 @@ static size_t lds_limit() {
 }
 
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
-                 hipStream_t s, const int *skip, const double *w, const int *mdone) {
+                 hipStream_t s, const int *skip, const double *w, const int *mdone, bool finish_halo) {
     const int64_t nt = F->nt, nv = F->nv;
     if (nv == 0) return;
     if (nt == 0) {
@@ -1062,7 +1062,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
             if (F->model == EBBX_STVK) launch_model<double, EBBX_STVK>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
             else launch_model<double, EBBX_NH>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
         }
-        if (F->sh_n > 0) {
+        if (F->sh_n > 0 && finish_halo) {
             const dim3 g(grid_n(F->sh_n, 256, 1ll << 20));
             const double *hl = (const double *)F->halo.get();
             const int32_t *sv = F->sh_vert.as<int32_t>();
@@ -1364,6 +1364,19 @@ int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hip
     return (int64_t)hb;
 }
 
+HaloView elem_halo_view(const ebbx_fem_s *F) {
+    HaloView h{};
+    const bool block = F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS;
+    if (!block || F->sh_n == 0 || F->nt == 0) return h;
+    h.row = F->sh_row.as<int32_t>();
+    h.tab = F->sh_tab.as<int4>();
+    h.ptr = F->sh_ptr.as<int32_t>();
+    h.pos = F->sh_pos.as<int32_t>();
+    h.halo = F->halo.as<double>();
+    h.nc = F->sh_nc;
+    return h;
+}
+
 // ---- block tables -----------------------------------------------------------------------
 
 // Tets are cut into blocks of bt consecutive rows.  Per block: the sorted set of
@@ -1505,6 +1518,10 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
     up(F->sh_vert, sh_vert.data(), sh_vert.size() * sizeof(int32_t));
     up(F->sh_ptr, sh_ptr.data(), sh_ptr.size() * sizeof(int32_t));
     up(F->sh_pos, sh_pos.data(), sh_pos.size() * sizeof(int32_t));
+    // per vertex: its row in the shared-vertex table, or -1 (the block stores it)
+    std::vector<int32_t> shrow((size_t)std::max<int64_t>(nv, 1), -1);
+    for (size_t r = 0; r < sh_vert.size(); ++r) shrow[(size_t)sh_vert[r]] = (int32_t)r;
+    up(F->sh_row, shrow.data(), shrow.size() * sizeof(int32_t));
     // fixed-width rows of halo positions when no vertex has more than 16 entries
     int32_t maxm = 0;
     for (size_t r = 0; r + 1 < sh_ptr.size(); ++r) maxm = std::max(maxm, sh_ptr[r + 1] - sh_ptr[r]);

@@ -53,8 +53,24 @@ struct ElemArgs {
 // Launch the element map `op` with the FEM's current strategy; result into
 // out (3, nv) (+= if accumulate).  For OP_DIAG, u is ignored and out receives
 // the raw stiffness diagonal K[(v,c),(v,c)].
+// finish_halo = false (block strategies) leaves the shared vertices' sums in the
+// halo for a consumer that reads them through elem_halo_view.
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
-                 hipStream_t s, const int *skip = nullptr, const double *w = nullptr, const int *mdone = nullptr);
+                 hipStream_t s, const int *skip = nullptr, const double *w = nullptr, const int *mdone = nullptr,
+                 bool finish_halo = true);
+
+// The unfinished output of a block-strategy element map: vertex v's value is
+// out[v] when row[v] < 0, else the sum of its halo entries (row r of the
+// shared-vertex table, positions in block order; nc int4 chunks per row, or
+// the CSR form ptr/pos when nc = 0).  row == NULL: nothing to finish.
+struct HaloView {
+    const int32_t *row;
+    const int4 *tab;
+    const int32_t *ptr, *pos;
+    const double *halo;
+    int nc;
+};
+HaloView elem_halo_view(const ebbx_fem_s *F);
 // E_bar[t] += w_t . (cf f_t(d) + ck K_t(d) v) / E_t over the tets (no scatter; v unused if ck = 0).
 void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w, double cf, double ck,
                 double *E_bar, hipStream_t s);
@@ -118,7 +134,8 @@ struct ebbx_fem_s {
     int64_t blk_nverts = 0;    // entries of blk_verts over all blocks
     int64_t sh_n = 0;          // vertices summed from the halo (shared or untouched)
     int64_t halo_n = 0;        // halo entries
-    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_pos, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos, sh_tab;
+    ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_pos, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos, sh_tab,
+        sh_row;
     int32_t sh_nc = 0;         // int4 chunks per row of sh_tab (0: use the CSR form)
     bool blocks_built = false;
     // owner strategy tables

@@ -160,9 +160,45 @@ __global__ __launch_bounds__(VT) void k_step_init(CGState *st, const double *par
     }
 }
 
-// q = Pi (M p - dt^2 y); chunk partial p.q
+// Vertex v's value of an element-map output that may still have its shared
+// vertices' sums in the halo (same summation order as the halo pass).
+__device__ __forceinline__ void finished(const HaloView &h, const double *y, int64_t nv, int64_t v, double *o) {
+    const int32_t r = h.row ? h.row[v] : -1;
+    if (r < 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) o[k] = y[k * nv + v];
+        return;
+    }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (h.nc > 0) {
+        for (int c = 0; c < h.nc; ++c) {
+            const int4 q = h.tab[(size_t)r * h.nc + c];
+            const int32_t p4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (p4[k] >= 0) {
+                    const double *hq = h.halo + 3 * (size_t)p4[k];
+                    a0 += hq[0];
+                    a1 += hq[1];
+                    a2 += hq[2];
+                }
+        }
+    } else {
+        for (int32_t j = h.ptr[r]; j < h.ptr[r + 1]; ++j) {
+            const double *hq = h.halo + 3 * (size_t)h.pos[j];
+            a0 += hq[0];
+            a1 += hq[1];
+            a2 += hq[2];
+        }
+    }
+    o[0] = a0;
+    o[1] = a1;
+    o[2] = a2;
+}
+
+// q = Pi (M p - dt^2 y); chunk partial p.q (y finished here if the element map left it in the halo)
 __global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
-                                              double dt, const CGState *st, Chunks ch, double *part) {
+                                              double dt, const CGState *st, Chunks ch, HaloView hv, double *part) {
     __shared__ double s4[4];
     const int c = blockIdx.x;
     if (st[ch.mesh[c]].done) return;   // uniform over the block
@@ -171,11 +207,13 @@ __global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, con
     if (v < ch.hi[c]) {
         const double m = mass[v];
         const bool pin = pinned[v] != 0;
+        double y[3];
+        finished(hv, w.y, nv, v, y);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
             const double p = w.p[i];
-            const double q = pin ? 0.0 : m * p - dt * dt * w.y[i];
+            const double q = pin ? 0.0 : m * p - dt * dt * y[k];
             w.q[i] = q;
             pq += p * q;
         }
@@ -453,12 +491,15 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     // past convergence cost a launch each, so the chunks stay short.
     S.first_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 32 : 128));
     S.chunk_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 16 : 128));
+    // K p: a block-strategy element map leaves its shared vertices in the halo and
+    // k_cg_Ap finishes them as it reads y (one launch and one y round trip fewer)
+    const HaloView hv = elem_halo_view(F);
     auto iterations = [&](int count) {
         for (int it = 0; it < count && it < p.maxit; ++it) {
             elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &ctl->all_done, nullptr,
-                        nm > 1 ? (const int *)(ctl + 1) : nullptr);
+                        nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr);
             hipLaunchKernelGGL(k_cg_Ap, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
-                               nv, p.dt, (const CGState *)st, S.ch, part);
+                               nv, p.dt, (const CGState *)st, S.ch, hv, part);
             hipLaunchKernelGGL(k_cg_alpha, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, ctl);
             hipLaunchKernelGGL(k_cg_update, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch, part);
             hipLaunchKernelGGL(k_cg_beta, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, p.tol, p.maxit,
