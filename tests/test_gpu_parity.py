@@ -391,3 +391,38 @@ def test_locality_workload_full_size(order):
         if st == "owner":
             assert torch.equal(f, seg_f) and torch.equal(k, seg_k)
     mesh.fem.close()
+
+
+@pytest.mark.parametrize("strat", STRATS)
+def test_empty_and_isolated(strat):
+    """Degenerate shapes: no tets at all (every output zero, the step is free fall of the free
+    vertices), and a mesh whose vertices include ones no tet touches."""
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1], [3, 3, 3]], dtype=float)
+    tets0 = np.zeros((0, 4), dtype=np.int32)
+    mesh = ebbx.FemMesh(X, tets0, np.array([1, 0, 0, 0, 0], np.uint8), model=1, elem_prec=ebbx.F64,
+                        strategy=_strat(strat))
+    d = mesh.to_dev(0.01 * np.arange(15, dtype=float).reshape(5, 3))
+    f = mesh.fem.forces(d, f=torch.full_like(d, 7.0))
+    assert float(f.abs().max()) == 0.0
+    assert float(mesh.fem.kmul(d, d.clone()).abs().max()) == 0.0
+    assert float(mesh.fem.mass().abs().max()) == 0.0
+    # no tets: no mass, no force, so the right-hand side is exactly zero (0 iterations, v kept)
+    vv = torch.zeros_like(d)
+    st = ebbx.stats_fetch(mesh.fem.implicit_step(d.clone(), vv, 1e-3, tol=1e-8, maxit=10))
+    assert st.status == ebbx.OK and st.iters == 0 and float(vv.abs().max()) == 0.0
+    mesh.fem.close()
+    # one tet plus an isolated vertex: the isolated vertex gets exactly zero, the step moves it
+    # not at all (zero mass row is pinned here), the tet's corners match the oracle
+    tets1 = np.array([[0, 1, 2, 3]], dtype=np.int32)
+    pin = np.array([0, 0, 0, 0, 1], np.uint8)
+    mesh = ebbx.FemMesh(X, tets1, pin, model=1, elem_prec=ebbx.F64, strategy=_strat(strat))
+    ref = oracle.FEM.create(1, X, tets1, 1e5, 0.3, pinned=pin)
+    dh = 0.01 * mg.direction(mg.Mesh(X=X, tets=tets1, pinned=pin), 3)
+    dh[4] = 0.0
+    f = mesh.from_dev(mesh.fem.forces(mesh.to_dev(dh)))
+    assert nerr(f, ref.forces(dh)) <= 1e-10 and np.all(f[4] == 0.0)
+    dd, vv = mesh.to_dev(dh), mesh.to_dev(np.zeros_like(dh))
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(dd, vv, 1e-3, tol=1e-12, maxit=50))
+    d1, v1, _dv, so = ref.implicit_step(dh, np.zeros_like(dh), 1e-3, tol=1e-12, maxit=50)
+    assert s.status == ebbx.OK and nerr(mesh.from_dev(vv), v1) <= 1e-10
+    mesh.fem.close()
