@@ -62,10 +62,14 @@ __device__ __forceinline__ double block_sum(double x, double *s4) {
     return (s4[0] + s4[1]) + (s4[2] + s4[3]);
 }
 
-// Fixed-order sum of the partials (stride 2, offset o) of chunks [c0, c1).
+// Chunk partials, 4 doubles per chunk: [0] p.q, [1] r.r, [2 + parity] r.z of the
+// iterations of that parity (the initial residual counts as parity 1).
+constexpr int PQ = 0, RR = 1, RZ = 2;
+
+// Fixed-order sum of the partials at offset o of chunks [c0, c1).
 __device__ __forceinline__ double sum_parts(const double *part, int c0, int c1, int o, double *s4) {
     double acc = 0.0;
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += VT) acc += part[2 * c + o];
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += VT) acc += part[4 * c + o];
     return block_sum(acc, s4);
 }
 
@@ -132,8 +136,8 @@ __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, 
     rz = block_sum(rz, s4);
     rr = block_sum(rr, s4);
     if (threadIdx.x == 0) {
-        part[2 * c] = rz;
-        part[2 * c + 1] = rr;
+        part[4 * c + RZ + 1] = rz;
+        part[4 * c + RR] = rr;
     }
 }
 
@@ -142,8 +146,8 @@ __global__ __launch_bounds__(VT) void k_step_init(CGState *st, const double *par
                                                   const unsigned long long *n_inv, SolveCtl *ctl) {
     __shared__ double s4[4];
     const int m = blockIdx.x;
-    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 0, s4);
-    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 1, s4);
+    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ + 1, s4);
+    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RR, s4);
     if (threadIdx.x == 0) {
         CGState &s = st[m];
         s.rz = rz;
@@ -219,14 +223,14 @@ __global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, con
         }
     }
     pq = block_sum(pq, s4);
-    if (threadIdx.x == 0) part[2 * c] = pq;
+    if (threadIdx.x == 0) part[4 * c + PQ] = pq;
 }
 
 __global__ __launch_bounds__(VT) void k_cg_alpha(CGState *st, const double *part, Chunks ch, SolveCtl *ctl) {
     __shared__ double s4[4];
     const int m = blockIdx.x;
     if (st[m].done) return;
-    const double pq = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 0, s4);
+    const double pq = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], PQ, s4);
     if (threadIdx.x == 0) {
         CGState &s = st[m];
         s.pq = pq;
@@ -264,8 +268,8 @@ __global__ __launch_bounds__(VT) void k_cg_update(StepVec w, int64_t nv, const C
     rz = block_sum(rz, s4);
     rr = block_sum(rr, s4);
     if (threadIdx.x == 0) {
-        part[2 * c] = rz;
-        part[2 * c + 1] = rr;
+        part[4 * c + RZ] = rz;
+        part[4 * c + RR] = rr;
     }
 }
 
@@ -274,8 +278,8 @@ __global__ __launch_bounds__(VT) void k_cg_beta(CGState *st, const double *part,
     __shared__ double s4[4];
     const int m = blockIdx.x;
     if (st[m].done) return;
-    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 0, s4);
-    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], 1, s4);
+    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ, s4);
+    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RR, s4);
     if (threadIdx.x == 0) {
         CGState &s = st[m];
         s.iters += 1;
@@ -297,6 +301,94 @@ __global__ __launch_bounds__(VT) void k_cg_p(StepVec w, int64_t nv, const CGStat
     const CGState &s = st[ch.mesh[c]];
     if (s.done) return;
     const double beta = s.beta;
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    if (v < ch.hi[c])
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            w.p[i] = w.z[i] + beta * w.p[i];
+        }
+}
+
+// Fused forms for meshes of at most FUSE_CHUNKS chunks: every workgroup of a
+// mesh sums the mesh's chunk partials itself (the same fixed order in every
+// workgroup, so all of them see the same scalar) instead of a separate
+// one-workgroup-per-mesh kernel; the mesh's first chunk records the state.
+// r.z ping-pongs between two partial slots by iteration parity, so a
+// workgroup can still read the previous iteration's value.
+constexpr int FUSE_CHUNKS = 2048;
+
+// alpha = (r.z)_prev / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials (r.z, r.r)
+__global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGState *st, Chunks ch, double *part,
+                                                    int par, SolveCtl *ctl) {
+    __shared__ double s4[4];
+    const int c = blockIdx.x, m = ch.mesh[c];
+    if (st[m].done) return;   // uniform over the block
+    const double pq = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], PQ, s4);
+    const double rz0 = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ + (par ^ 1), s4);
+    const bool first = c == ch.cptr[m] && threadIdx.x == 0;
+    if (!(pq > 0.0)) {   // breakdown: every workgroup of the mesh sees it and leaves x, r alone
+        if (first) {
+            st[m].pq = pq;
+            st[m].status = EBBX_E_NOT_SPD;
+            mark_done(st[m], ctl, m);
+        }
+        return;
+    }
+    const double alpha = rz0 / pq;
+    if (first) {
+        st[m].pq = pq;
+        st[m].alpha = alpha;
+    }
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    double rz = 0.0, rr = 0.0;
+    if (v < ch.hi[c]) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            w.x[i] += alpha * w.p[i];
+            const double r = w.r[i] - alpha * w.q[i];
+            const double z = r / w.diag[i];
+            w.r[i] = r;
+            w.z[i] = z;
+            rz += r * z;
+            rr += r * r;
+        }
+    }
+    rz = block_sum(rz, s4);
+    rr = block_sum(rr, s4);
+    if (threadIdx.x == 0) {
+        part[4 * c + RZ + par] = rz;
+        part[4 * c + RR] = rr;
+    }
+}
+
+// stopping test; beta = (r.z)_new / (r.z)_prev; p = z + beta p
+__global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *st, Chunks ch, const double *part,
+                                               int par, double tol, int maxit, SolveCtl *ctl) {
+    __shared__ double s4[4];
+    const int c = blockIdx.x, m = ch.mesh[c];
+    if (st[m].done) return;   // uniform; a mesh marked done by its first chunk needs no new p
+    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ + par, s4);
+    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RR, s4);
+    const double rz0 = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ + (par ^ 1), s4);
+    const bool conv = sqrt(rr) <= tol * st[m].bnorm || rz == 0.0;
+    const double beta = rz / rz0;
+    if (c == ch.cptr[m] && threadIdx.x == 0) {
+        CGState &s = st[m];
+        const int it = s.iters + 1;
+        s.iters = it;
+        s.rr = rr;
+        if (conv) {
+            s.converged = 1;
+            mark_done(s, ctl, m);
+        } else {
+            s.beta = beta;
+            s.rz = rz;
+            if (it >= maxit) mark_done(s, ctl, m);
+        }
+    }
+    if (conv) return;
     const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
     if (v < ch.hi[c])
 #pragma unroll
@@ -412,6 +504,7 @@ struct ebbx_fem_s::Step {
     hipStream_t cap = nullptr;
     int first_iters = 0, chunk_iters = 0;
     bool valid = false;   // graphs match the parameters below
+    bool fused = true;    // one-kernel alpha and beta (every mesh has at most FUSE_CHUNKS chunks)
     // parameters baked into the graphs
     double dt = -1, g[3] = {0, 0, 0}, tol = -1;
     int maxit = -1, precond = -1, strategy = -1, block = -1;
@@ -491,6 +584,9 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     // past convergence cost a launch each, so the chunks stay short.
     S.first_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 32 : 128));
     S.chunk_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 16 : 128));
+    // the fused kernels pick r.z slots by iteration parity: later chunks must start at even iterations
+    if (p.maxit > S.first_iters && ((S.first_iters | S.chunk_iters) & 1))
+        fail(EBBX_E_STATE, "CG chunk sizes must be even");
     // K p: a block-strategy element map leaves its shared vertices in the halo and
     // k_cg_Ap finishes them as it reads y (one launch and one y round trip fewer)
     const HaloView hv = elem_halo_view(F);
@@ -500,11 +596,18 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
                         nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr);
             hipLaunchKernelGGL(k_cg_Ap, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
                                nv, p.dt, (const CGState *)st, S.ch, hv, part);
-            hipLaunchKernelGGL(k_cg_alpha, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, ctl);
-            hipLaunchKernelGGL(k_cg_update, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch, part);
-            hipLaunchKernelGGL(k_cg_beta, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, p.tol, p.maxit,
-                               ctl);
-            hipLaunchKernelGGL(k_cg_p, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch);
+            if (S.fused) {
+                const int par = it & 1;   // chunks after the first start at even iterations
+                hipLaunchKernelGGL(k_cg_update_f, dim3(nch), dim3(VT), 0, cs, S.w, nv, st, S.ch, part, par, ctl);
+                hipLaunchKernelGGL(k_cg_p_f, dim3(nch), dim3(VT), 0, cs, S.w, nv, st, S.ch, (const double *)part, par,
+                                   p.tol, p.maxit, ctl);
+            } else {
+                hipLaunchKernelGGL(k_cg_alpha, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, ctl);
+                hipLaunchKernelGGL(k_cg_update, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch, part);
+                hipLaunchKernelGGL(k_cg_beta, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, p.tol,
+                                   p.maxit, ctl);
+                hipLaunchKernelGGL(k_cg_p, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch);
+            }
         }
     };
     // the preamble graph also holds the first chunk, so a solve that converges
@@ -572,7 +675,10 @@ void ensure_step(ebbx_fem_s *F, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(cp + 2 * nch, mesh.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(cp + 3 * nch, cptr.data(), (nm + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
     S->ch = Chunks{cp, cp + nch, cp + 2 * nch, cp + 3 * nch};
-    S->part.reset((size_t)nch * 2 * sizeof(double), s);
+    S->part.reset((size_t)nch * 4 * sizeof(double), s);
+    int32_t most = 0;
+    for (int64_t m = 0; m < nm; ++m) most = std::max(most, cptr[(size_t)m + 1] - cptr[(size_t)m]);
+    S->fused = most <= FUSE_CHUNKS;
     S->state.reset((size_t)std::max<int64_t>(nm, 1) * sizeof(CGState), s);
     S->ctl.reset(sizeof(SolveCtl) + (size_t)std::max<int64_t>(nm, 1) * sizeof(int), s);
     HIPCHK(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));

@@ -426,3 +426,20 @@ def test_empty_and_isolated(strat):
     d1, v1, _dv, so = ref.implicit_step(dh, np.zeros_like(dh), 1e-3, tol=1e-12, maxit=50)
     assert s.status == ebbx.OK and nerr(mesh.from_dev(vv), v1) <= 1e-10
     mesh.fem.close()
+
+
+def test_step_large_mesh():
+    """81^3 cube (3,188,646 tets, 551,368 vertices: more than 2048 vertex chunks, so the solver
+    reduces its dot products with one workgroup per mesh instead of in every workgroup):
+    one tolerance-terminated step, StVK FP32, against the oracle."""
+    m = mg.kuhn_cube(81)
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=0, elem_prec=ebbx.F32, E=1e5, nu=0.3,
+                        strategy=ebbx.STRAT_BLOCK, morton=True)
+    ref = oracle.FEM.create(0, m.X, m.tets, 1e5, 0.3, pinned=m.pinned)
+    z = np.zeros((m.nv, 3))
+    d, v = mesh.to_dev(z), mesh.to_dev(z)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-3, tol=1e-8, maxit=500))
+    _d1, v1, _dv, so = ref.implicit_step(z, z, 1e-3, tol=1e-8, maxit=500)
+    assert s.status == ebbx.OK and abs(s.iters - so.iters) <= 2
+    assert nerr(mesh.from_dev(v), v1) <= 1e-5
+    mesh.fem.close()
