@@ -73,6 +73,34 @@ __device__ __forceinline__ double sum_parts(const double *part, int c0, int c1, 
     return block_sum(acc, s4);
 }
 
+// Three fixed-order sums at once (offsets o0, o1, o2), each with exactly the
+// operation order of sum_parts, sharing the barriers.
+__device__ __forceinline__ void sum_parts3(const double *part, int c0, int c1, int o0, int o1, int o2, double *s12,
+                                           double &r0, double &r1, double &r2) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += VT) {
+        a0 += part[4 * c + o0];
+        a1 += part[4 * c + o1];
+        a2 += part[4 * c + o2];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+        a2 += __shfl_xor(a2, o, 64);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        s12[threadIdx.x >> 6] = a0;
+        s12[4 + (threadIdx.x >> 6)] = a1;
+        s12[8 + (threadIdx.x >> 6)] = a2;
+    }
+    __syncthreads();
+    r0 = (s12[0] + s12[1]) + (s12[2] + s12[3]);
+    r1 = (s12[4] + s12[5]) + (s12[6] + s12[7]);
+    r2 = (s12[8] + s12[9]) + (s12[10] + s12[11]);
+}
+
 // One thread of the mesh's block marks mesh m finished.
 __device__ __forceinline__ void mark_done(CGState &st, SolveCtl *ctl, int m) {
     st.done = 1;
@@ -318,14 +346,28 @@ __global__ __launch_bounds__(VT) void k_cg_p(StepVec w, int64_t nv, const CGStat
 // workgroup can still read the previous iteration's value.
 constexpr int FUSE_CHUNKS = 2048;
 
-// alpha = (r.z)_prev / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials (r.z, r.r)
+// alpha = (r.z)_prev / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials (r.z, r.r).
+// The vector loads are issued before the partial sums, so they overlap them.
 __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGState *st, Chunks ch, double *part,
                                                     int par, SolveCtl *ctl) {
-    __shared__ double s4[4];
+    __shared__ double s12[12];
     const int c = blockIdx.x, m = ch.mesh[c];
     if (st[m].done) return;   // uniform over the block
-    const double pq = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], PQ, s4);
-    const double rz0 = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ + (par ^ 1), s4);
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    const bool in = v < ch.hi[c];
+    double x[3] = {0, 0, 0}, p[3] = {0, 0, 0}, r[3] = {0, 0, 0}, q[3] = {0, 0, 0}, dg[3] = {1, 1, 1};
+    if (in)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            x[k] = w.x[i];
+            p[k] = w.p[i];
+            r[k] = w.r[i];
+            q[k] = w.q[i];
+            dg[k] = w.diag[i];
+        }
+    double pq, rz0, unused;
+    sum_parts3(part, ch.cptr[m], ch.cptr[m + 1], PQ, RZ + (par ^ 1), PQ, s12, pq, rz0, unused);
     const bool first = c == ch.cptr[m] && threadIdx.x == 0;
     if (!(pq > 0.0)) {   // breakdown: every workgroup of the mesh sees it and leaves x, r alone
         if (first) {
@@ -340,23 +382,22 @@ __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGSta
         st[m].pq = pq;
         st[m].alpha = alpha;
     }
-    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
     double rz = 0.0, rr = 0.0;
-    if (v < ch.hi[c]) {
+    if (in) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
-            w.x[i] += alpha * w.p[i];
-            const double r = w.r[i] - alpha * w.q[i];
-            const double z = r / w.diag[i];
-            w.r[i] = r;
+            w.x[i] = x[k] + alpha * p[k];
+            const double rn = r[k] - alpha * q[k];
+            const double z = rn / dg[k];
+            w.r[i] = rn;
             w.z[i] = z;
-            rz += r * z;
-            rr += r * r;
+            rz += rn * z;
+            rr += rn * rn;
         }
     }
-    rz = block_sum(rz, s4);
-    rr = block_sum(rr, s4);
+    rz = block_sum(rz, s12);
+    rr = block_sum(rr, s12);
     if (threadIdx.x == 0) {
         part[4 * c + RZ + par] = rz;
         part[4 * c + RR] = rr;
@@ -366,12 +407,20 @@ __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGSta
 // stopping test; beta = (r.z)_new / (r.z)_prev; p = z + beta p
 __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *st, Chunks ch, const double *part,
                                                int par, double tol, int maxit, SolveCtl *ctl) {
-    __shared__ double s4[4];
+    __shared__ double s12[12];
     const int c = blockIdx.x, m = ch.mesh[c];
     if (st[m].done) return;   // uniform; a mesh marked done by its first chunk needs no new p
-    const double rz = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ + par, s4);
-    const double rr = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RR, s4);
-    const double rz0 = sum_parts(part, ch.cptr[m], ch.cptr[m + 1], RZ + (par ^ 1), s4);
+    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    const bool in = v < ch.hi[c];
+    double z[3] = {0, 0, 0}, p[3] = {0, 0, 0};
+    if (in)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            z[k] = w.z[k * nv + v];
+            p[k] = w.p[k * nv + v];
+        }
+    double rz, rr, rz0;
+    sum_parts3(part, ch.cptr[m], ch.cptr[m + 1], RZ + par, RR, RZ + (par ^ 1), s12, rz, rr, rz0);
     const bool conv = sqrt(rr) <= tol * st[m].bnorm || rz == 0.0;
     const double beta = rz / rz0;
     if (c == ch.cptr[m] && threadIdx.x == 0) {
@@ -388,14 +437,9 @@ __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *s
             if (it >= maxit) mark_done(s, ctl, m);
         }
     }
-    if (conv) return;
-    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
-    if (v < ch.hi[c])
+    if (conv || !in) return;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int64_t i = k * nv + v;
-            w.p[i] = w.z[i] + beta * w.p[i];
-        }
+    for (int k = 0; k < 3; ++k) w.p[k * nv + v] = z[k] + beta * p[k];
 }
 
 __global__ void k_copy_in(const double *d, const double *v, double *dn, double *vn, int64_t n) {
