@@ -37,6 +37,13 @@
  *    convergence) are reported in device-side stats read by ebbx_stats_fetch.
  *  - Threads: calls on different objects may come from different threads;
  *    calls on one object must not overlap.
+ *  - Streams of one FEM domain: its element calls share library scratch (the
+ *    block strategies' halo, the segmented strategy's partials) and its steps
+ *    share the solver's vectors, so work on one domain must be ordered: one
+ *    stream, or events between streams.  Different domains are independent.
+ *  - Rounding: the SEG, BLOCK and OWNER strategies and every CG reduction sum
+ *    in a fixed order, so their results are bitwise reproducible run to run;
+ *    ATOMIC and BLOCK_LDS are not.
  */
 #ifndef EBBX_H
 #define EBBX_H
