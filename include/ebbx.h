@@ -158,8 +158,9 @@ enum { EBBX_STVK = 0, EBBX_NH = 1 };
  *   SEG:       per-corner partials, then a vertex-owned sum over the grouping's
  *              incidence in fixed order (bitwise deterministic);
  *   BLOCK:     consecutive tets form blocks (best after Morton reordering);
- *              a block stages its vertices' fields in LDS, sums each vertex's
- *              contributions over a precomputed incidence list in fixed order,
+ *              a block stages its vertices' fields in LDS, writes each tet
+ *              corner's result to its row of the block's precomputed incidence
+ *              order, sums each vertex's contiguous rows in fixed order,
  *              stores the vertices whose incident tets all lie in the block,
  *              and writes partial sums of the others to a halo buffer that a
  *              vertex pass sums in block order: no global atomics, bitwise

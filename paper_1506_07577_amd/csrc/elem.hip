@@ -9,16 +9,20 @@
 // so that single precision keeps its accuracy near the rest shape (no F - I
 // or F - F^-T cancellation).
 //
-// Three reductions:
+// Four reductions:
 //  - ATOMIC: one thread per tet, FP64 device-scope atomics (the paper's GPU
 //    field reduction);
 //  - SEG:    one thread per tet writes its per-corner partials, then one thread
 //    per vertex sums them over the grouping's incidence in a fixed order;
 //  - BLOCK:  a workgroup takes a block of consecutive (Morton-ordered) tets,
-//    stages the block's vertices in LDS, evaluates, reduces into LDS, stores
-//    the vertices it owns outright and writes partials of vertices shared with
-//    other blocks to a halo buffer that a vertex pass sums in a fixed order.
-//    No global atomics.
+//    stages the block's vertices in LDS, evaluates, writes each corner's result
+//    to its row of the block's incidence order, sums each vertex's rows in a
+//    fixed order, stores the vertices it owns outright and writes partials of
+//    vertices shared with other blocks to a halo buffer that a vertex pass sums
+//    in block order.  No global atomics (BLOCK_LDS: the in-block sums with LDS
+//    atomics instead of rows);
+//  - OWNER:  a workgroup owns a range of vertices and evaluates every tet that
+//    touches them (boundary tets once per block), so no halo is needed.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
