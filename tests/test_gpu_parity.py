@@ -443,3 +443,34 @@ def test_step_large_mesh():
     assert s.status == ebbx.OK and abs(s.iters - so.iters) <= 2
     assert nerr(mesh.from_dev(v), v1) <= 1e-5
     mesh.fem.close()
+
+
+def test_randomized_small_meshes():
+    """Seeded sweep: 12 jittered and scrambled cubes of side 1..6 with random material, model,
+    precision, strategy and block size; forces, K u and the Jacobi diagonal against the oracle."""
+    rng = np.random.default_rng(2024)
+    blocks = {"atomic": [64, 128, 256], "seg": [64, 256], "block": [64, 128, 256, 512],
+              "block_lds": [64, 256], "owner": [64, 128]}
+    for case in range(12):
+        n = int(rng.integers(1, 7))
+        m = mg.jitter(mg.kuhn_cube(n), 0.01, seed=int(rng.integers(1 << 30)))
+        if rng.random() < 0.5:
+            m, _, _ = mg.scramble(m, seed=int(rng.integers(1 << 30)))
+        model = int(rng.integers(0, 2))
+        prec = "f64" if rng.random() < 0.5 else "f32"
+        strat = STRATS[int(rng.integers(0, len(STRATS)))]
+        blk = blocks[strat][int(rng.integers(0, len(blocks[strat])))]
+        E = float(10 ** rng.uniform(4, 6))
+        nu = float(rng.uniform(0.2, 0.45))
+        morton = bool(rng.random() < 0.5)
+        mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=model, elem_prec=_prec(prec), E=E, nu=nu,
+                            strategy=_strat(strat), block=blk, morton=morton)
+        ref = oracle.FEM.create(model, m.X, m.tets, E, nu, pinned=m.pinned)
+        d = mg.perturbed_state(m, 0.02, seed=int(rng.integers(1 << 30)))
+        u = mg.direction(m, int(rng.integers(1 << 30)))
+        dd, ud = mesh.to_dev(d), mesh.to_dev(u)
+        tag = (case, n, model, prec, strat, blk, morton)
+        assert nerr(mesh.from_dev(mesh.fem.forces(dd)), ref.forces(d)) <= TOL[prec], tag
+        assert nerr(mesh.from_dev(mesh.fem.kmul(dd, ud)), ref.kmul(d, u)) <= TOL[prec], tag
+        assert nerr(mesh.from_dev(mesh.fem.jacobi_diag(dd, 1e-3)), ref.jacobi_diag(d, 1e-3)) <= TOL[prec], tag
+        mesh.fem.close()
