@@ -65,8 +65,8 @@ def _load():
     lib.orc_tmul.argtypes = base + [P, P, P, P]
     lib.orc_energy.argtypes = base + [P, P]
     lib.orc_jacobi_diag.argtypes = base + [P, D, P, P]
-    lib.orc_implicit_step.argtypes = base + [P, P, D, P, D, I32, I32, P, P, P, P]
-    lib.orc_step_vjp.argtypes = base + [P, P, P, D, D, I32, I32, P, P, P, P, P, P, P, P]
+    lib.orc_implicit_step.argtypes = base + [P, P, D, P, D, D, D, I32, I32, P, P, P, P]
+    lib.orc_step_vjp.argtypes = base + [P, P, P, D, D, D, D, I32, I32, P, P, P, P, P, P, P, P]
     lib.orc_group_by.argtypes = [I64, I64, P, P, P]
     lib.orc_morton.argtypes = [I64, I64, P, P, P, P, P]
     for f in ("orc_precompute", "orc_stress", "orc_dstress", "orc_d2stress",
@@ -230,21 +230,25 @@ class FEM:
         return diag
 
     def implicit_step(self, d, v, dt, g=(0.0, 0.0, -9.81), tol=0.0, maxit=100,
-                      precond=PRECOND_JACOBI, allow_not_converged=True):
-        """Returns (d', v', dv, stats) without touching the inputs."""
+                      precond=PRECOND_JACOBI, allow_not_converged=True, alpha=0.0, beta=0.0):
+        """Returns (d', v', dv, stats) without touching the inputs.
+
+        alpha, beta: Rayleigh damping D = alpha M - beta K (Vega's step computes
+        damping with the forces and the stiffness: Performance Evaluation)."""
         d = _f64(d, (self.nv, 3)).copy()
         v = _f64(v, (self.nv, 3)).copy()
         g = _f64(g)
         dv = np.zeros((self.nv, 3))
         st = Stats()
         rc = _load().orc_implicit_step(*self._base(), _p(self.mass), _p(self.pinned), dt, _p(g),
-                                       tol, maxit, precond, _p(d), _p(v), _p(dv), C.byref(st))
+                                       alpha, beta, tol, maxit, precond, _p(d), _p(v), _p(dv),
+                                       C.byref(st))
         allow = (OK, E_NOT_CONVERGED) if allow_not_converged else (OK,)
         _chk(rc, "implicit_step", allow)
         return d, v, dv, st
 
     def step_vjp(self, d_n, v_np1, gx, gv, dt, tol=1e-12, maxit=10000,
-                 precond=PRECOND_JACOBI):
+                 precond=PRECOND_JACOBI, alpha=0.0, beta=0.0):
         """Returns (d_bar, v_bar, E_bar, stats) of one implicit step."""
         d_n, v_np1, gx, gv = (_f64(x, (self.nv, 3)) for x in (d_n, v_np1, gx, gv))
         d_bar = np.zeros((self.nv, 3))
@@ -252,25 +256,28 @@ class FEM:
         E_bar = np.zeros(self.nt)
         st = Stats()
         rc = _load().orc_step_vjp(*self._base(), _p(self.E), _p(self.mass), _p(self.pinned),
-                                  dt, tol, maxit, precond, _p(d_n), _p(v_np1), _p(gx), _p(gv),
+                                  dt, alpha, beta, tol, maxit, precond, _p(d_n), _p(v_np1),
+                                  _p(gx), _p(gv),
                                   _p(d_bar), _p(v_bar), _p(E_bar), C.byref(st))
         _chk(rc, "step_vjp", (OK, E_NOT_CONVERGED))
         return d_bar, v_bar, E_bar, st
 
 
 def trajectory(fem: FEM, d0, v0, steps, dt, tol, maxit, g=(0.0, 0.0, -9.81),
-               precond=PRECOND_JACOBI):
+               precond=PRECOND_JACOBI, alpha=0.0, beta=0.0):
     """Run `steps` implicit steps; returns the list of (d, v) states 0..steps."""
     states = [(np.array(d0, dtype=np.float64), np.array(v0, dtype=np.float64))]
     d, v = states[0]
     for _ in range(steps):
-        d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit, precond=precond)
+        d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit, precond=precond,
+                                           alpha=alpha, beta=beta)
         states.append((d, v))
     return states
 
 
 def trajectory_grad(fem: FEM, d0, v0, steps, dt, tol, maxit, target, X,
-                    g=(0.0, 0.0, -9.81), precond=PRECOND_JACOBI, checkpoint_every=0):
+                    g=(0.0, 0.0, -9.81), precond=PRECOND_JACOBI, checkpoint_every=0,
+                    alpha=0.0, beta=0.0):
     """Loss L = ||x_T - target||^2 with x = X + d; returns (L, dL/dd0, dL/dE).
 
     checkpoint_every = k > 0 keeps only every k-th state and recomputes each
@@ -280,7 +287,8 @@ def trajectory_grad(fem: FEM, d0, v0, steps, dt, tol, maxit, target, X,
     ckpt = {0: (np.array(d0, dtype=np.float64), np.array(v0, dtype=np.float64))}
     d, v = ckpt[0]
     for n in range(steps):
-        d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit, precond=precond)
+        d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit, precond=precond,
+                                           alpha=alpha, beta=beta)
         if (n + 1) % k == 0 and n + 1 < steps:
             ckpt[n + 1] = (d, v)
     xT = X + d
@@ -296,15 +304,15 @@ def trajectory_grad(fem: FEM, d0, v0, steps, dt, tol, maxit, target, X,
         d, v = ckpt[s0]
         for _ in range(s0, end - 1):
             d, v, _dv, _st = fem.implicit_step(d, v, dt, g=g, tol=tol, maxit=maxit,
-                                               precond=precond)
+                                               precond=precond, alpha=alpha, beta=beta)
             states.append((d, v))
         # reverse the steps s0 .. end-1; step n maps states[n-s0] -> n+1
         for n in range(end - 1, s0 - 1, -1):
             d_n, v_n = states[n - s0]
             _d1, v_np1, _dv, _st = fem.implicit_step(d_n, v_n, dt, g=g, tol=tol, maxit=maxit,
-                                                     precond=precond)
+                                                     precond=precond, alpha=alpha, beta=beta)
             d_bar, v_bar, eb, _ = fem.step_vjp(d_n, v_np1, gx, gv, dt, tol=tol, maxit=maxit,
-                                               precond=precond)
+                                               precond=precond, alpha=alpha, beta=beta)
             E_bar += eb
             gx, gv = d_bar, v_bar
         end = s0

@@ -414,14 +414,15 @@ typedef struct {
     const double *B, *V0, *mu, *lam, *mass, *d;
     const uint8_t *pinned;
     double dt;
+    double cm, ck;   /* A = cm M - ck K(d) */
 } sys_t;
 
-/* q = Pi (M p - dt^2 K(d) p) */
+/* q = Pi (cm M p - ck K(d) p) */
 static int apply_A(const sys_t *s, const double *p, double *q) {
     int st = orc_kmul(s->model, s->nv, s->nt, s->tets, s->B, s->V0, s->mu, s->lam, s->d, p, q);
     if (st) return st;
     for (int64_t i = 0; i < 3 * s->nv; ++i) {
-        q[i] = s->mass[i / 3] * p[i] - s->dt * s->dt * q[i];
+        q[i] = s->cm * s->mass[i / 3] * p[i] - s->ck * q[i];
         if (s->pinned && s->pinned[i / 3]) q[i] = 0.0;
     }
     return ORC_OK;
@@ -486,32 +487,49 @@ static int build_diag(const sys_t *s, int32_t precond, double **diag) {
     if (precond != ORC_PRECOND_JACOBI) return ORC_OK;
     *diag = malloc(sizeof(double) * (size_t)(3 * s->nv));
     if (!*diag) return ORC_E_ARG;
+    /* diag(A) = cm M - ck diag(K): the undamped diagonal M - dt^2 diag(K) at dt = 1
+     * and zero mass gives -diag(K) */
+    double *zero_m = calloc((size_t)(s->nv > 0 ? s->nv : 1), sizeof(double));
+    if (!zero_m) return ORC_E_ARG;
     int st = orc_jacobi_diag(s->model, s->nv, s->nt, s->tets, s->B, s->V0, s->mu, s->lam,
-                             s->mass, s->dt, s->d, *diag);
+                             zero_m, 1.0, s->d, *diag);
+    free(zero_m);
     if (st) return st;
-    for (int64_t i = 0; i < 3 * s->nv; ++i)
+    for (int64_t i = 0; i < 3 * s->nv; ++i) {
+        (*diag)[i] = s->cm * s->mass[i / 3] + s->ck * (*diag)[i];
         if (s->pinned && s->pinned[i / 3]) (*diag)[i] = 1.0;
+    }
     return ORC_OK;
 }
 
 int orc_implicit_step(int model, int64_t nv, int64_t nt, const int32_t *tets,
                       const double *B, const double *V0, const double *mu, const double *lam,
                       const double *mass, const uint8_t *pinned,
-                      double dt, const double g[3], double tol, int32_t maxit, int32_t precond,
+                      double dt, const double g[3], double alpha, double beta,
+                      double tol, int32_t maxit, int32_t precond,
                       double *d, double *v, double *dv_out, orc_stats *stats) {
+    /* Backward Euler with Rayleigh damping D = alpha M - beta K(d) (K = df/dx,
+     * so -K is the stiffness of the textbook form alpha M + beta K_s), linearised
+     * about (d, v):
+     *   M dv = dt (f(d + dt (v + dv)) + M g - D (v + dv)),  f(d + e) ~ f(d) + K e
+     *   => (M + dt D - dt^2 K) dv = dt (f + M g - D v + dt K v)
+     *   => A = (1 + dt alpha) M - (dt^2 + dt beta) K,
+     *      b = dt (f + M g - alpha M v + (dt + beta) K v). */
     int64_t n = 3 * nv;
-    sys_t s = {model, nv, nt, tets, B, V0, mu, lam, mass, d, pinned, dt};
+    sys_t s = {model, nv, nt, tets, B, V0, mu, lam, mass, d, pinned, dt,
+               1.0 + dt * alpha, dt * dt + dt * beta};
     double *f = malloc(sizeof(double) * (size_t)n), *kv = malloc(sizeof(double) * (size_t)n);
     double *b = malloc(sizeof(double) * (size_t)n), *dv = malloc(sizeof(double) * (size_t)n);
     double *diag = NULL;
     int st = ORC_E_ARG;
     if (!f || !kv || !b || !dv) goto done;
-    /* b = dt (f(d) + M g + dt K(d) v) */
+    /* b = dt (f(d) + M g - alpha M v + (dt + beta) K(d) v) */
     st = orc_forces(model, nv, nt, tets, B, V0, mu, lam, d, f);
     if (st) goto done;
     st = orc_kmul(model, nv, nt, tets, B, V0, mu, lam, d, v, kv);
     if (st) goto done;
-    for (int64_t i = 0; i < n; ++i) b[i] = dt * (f[i] + mass[i / 3] * g[i % 3] + dt * kv[i]);
+    for (int64_t i = 0; i < n; ++i)
+        b[i] = dt * (f[i] + mass[i / 3] * g[i % 3] - alpha * mass[i / 3] * v[i] + (dt + beta) * kv[i]);
     st = build_diag(&s, precond, &diag);
     if (st) goto done;
     st = pcg(&s, b, diag, tol, maxit, dv, stats);
@@ -530,17 +548,20 @@ done:
 int orc_step_vjp(int model, int64_t nv, int64_t nt, const int32_t *tets,
                  const double *B, const double *V0, const double *mu, const double *lam,
                  const double *E, const double *mass, const uint8_t *pinned,
-                 double dt, double tol, int32_t maxit, int32_t precond,
+                 double dt, double alpha, double beta, double tol, int32_t maxit, int32_t precond,
                  const double *d_n, const double *v_np1,
                  const double *gx, const double *gv,
                  double *d_bar, double *v_bar, double *E_bar, orc_stats *stats) {
-    /* Forward: v' = v + S b, b = dt f(d) + dt M g + dt^2 K(d) v, A = M - dt^2 K(d),
-     * d' = d + dt v'.  Reverse, with g^ = gv + dt gx and A w = Pi g^:
-     *   d_bar = gx + dt K w + dt^2 T[v', w]
-     *   v_bar = g^ + dt^2 K w
-     *   E_bar_t += (w_t . (dt f_t + dt^2 K_t v')) / E_t   (f, K linear in E_t) */
+    /* Forward (see orc_implicit_step): v' = v + dv, A dv = Pi b,
+     *   A = cm M - ck K(d), b = dt f(d) + dt M g - dt alpha M v + ck K(d) v,
+     *   cm = 1 + dt alpha, ck = dt^2 + dt beta, d' = d + dt v'.
+     * Reverse, with g^ = gv + dt gx and A w = Pi g^ (A symmetric):
+     *   d_bar = gx + dt K w + ck T[v, w] + ck T[dv, w] = gx + dt K w + ck T[v', w]
+     *   v_bar = g^ + ck K w - dt alpha M w
+     *   E_bar_t += (w_t . (dt f_t + ck K_t v')) / E_t   (f, K linear in E_t; M is not) */
     int64_t n = 3 * nv;
-    sys_t s = {model, nv, nt, tets, B, V0, mu, lam, mass, d_n, pinned, dt};
+    const double cm = 1.0 + dt * alpha, ck = dt * dt + dt * beta;
+    sys_t s = {model, nv, nt, tets, B, V0, mu, lam, mass, d_n, pinned, dt, cm, ck};
     double *gh = malloc(sizeof(double) * (size_t)n), *w = malloc(sizeof(double) * (size_t)n);
     double *kw = malloc(sizeof(double) * (size_t)n), *tw = malloc(sizeof(double) * (size_t)n);
     double *diag = NULL;
@@ -556,8 +577,8 @@ int orc_step_vjp(int model, int64_t nv, int64_t nt, const int32_t *tets,
     st = orc_tmul(model, nv, nt, tets, B, V0, mu, lam, d_n, v_np1, w, tw);
     if (st) goto done;
     for (int64_t i = 0; i < n; ++i) {
-        d_bar[i] = gx[i] + dt * kw[i] + dt * dt * tw[i];
-        v_bar[i] = gh[i] + dt * dt * kw[i];
+        d_bar[i] = gx[i] + dt * kw[i] + ck * tw[i];
+        v_bar[i] = gh[i] + ck * kw[i] - dt * alpha * mass[i / 3] * w[i];
     }
     if (E_bar) {
         for (int64_t t = 0; t < nt; ++t) {
@@ -569,7 +590,7 @@ int orc_step_vjp(int model, int64_t nv, int64_t nt, const int32_t *tets,
             if (st) goto done;
             st = orc_dstress(model, mu[t], lam[t], G, dF, dP);
             if (st) goto done;
-            for (int i = 0; i < 9; ++i) lin[i] = dt * P[i] + dt * dt * dP[i];
+            for (int i = 0; i < 9; ++i) lin[i] = dt * P[i] + ck * dP[i];
             /* w_t . (scatter of -V0 lin B^T) */
             double loc[12] = {0};
             int32_t id[4] = {0, 1, 2, 3};

@@ -65,12 +65,14 @@ int orc_jacobi_diag(int model, int64_t nv, int64_t nt, const int32_t *tets,
 
 typedef struct { int32_t iters, status; double rel_res; } orc_stats;
 
-/* One linearised backward-Euler step with masked (Jacobi-)PCG.  d and v are
+/* One linearised backward-Euler step with masked (Jacobi-)PCG and Rayleigh
+ * damping D = alpha M - beta K (alpha = beta = 0: undamped).  d and v are
  * updated in place.  dv_out (nullable) receives the velocity increment. */
 int orc_implicit_step(int model, int64_t nv, int64_t nt, const int32_t *tets,
                       const double *B, const double *V0, const double *mu, const double *lam,
                       const double *mass, const uint8_t *pinned,
-                      double dt, const double g[3], double tol, int32_t maxit, int32_t precond,
+                      double dt, const double g[3], double alpha, double beta,
+                      double tol, int32_t maxit, int32_t precond,
                       double *d, double *v, double *dv_out, orc_stats *stats);
 
 /* T[a, w] = grad_x (w^T K(x) a), overwriting out. */
@@ -84,7 +86,7 @@ int orc_tmul(int model, int64_t nv, int64_t nt, const int32_t *tets,
 int orc_step_vjp(int model, int64_t nv, int64_t nt, const int32_t *tets,
                  const double *B, const double *V0, const double *mu, const double *lam,
                  const double *E, const double *mass, const uint8_t *pinned,
-                 double dt, double tol, int32_t maxit, int32_t precond,
+                 double dt, double alpha, double beta, double tol, int32_t maxit, int32_t precond,
                  const double *d_n, const double *v_np1,
                  const double *gx, const double *gv,
                  double *d_bar, double *v_bar, double *E_bar, orc_stats *stats);

@@ -467,6 +467,97 @@ def test_pcg_breakdown_and_maxit():
 
 
 # --------------------------------------------------------------------------
+# Rayleigh damping (Vega's step computes damping with forces and stiffness:
+# Performance Evaluation); D = alpha M - beta K with K = df/dx
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("model", MODELS)
+def test_damped_rigid_translation(model):
+    # nothing pinned, at rest, uniform velocity: f = 0 and K annihilates translations,
+    # so every vertex follows the backward-Euler update of dv/dt = g - alpha v exactly
+    m = mg.jitter(mg.kuhn_cube(2), 0.02, seed=1)
+    fem = oracle.FEM.create(model, m.X, m.tets, 1e5, 0.3)
+    dt, alpha, beta = 1e-2, 4.0, 3e-3
+    g = np.array([0.5, -1.0, -9.81])
+    v0 = np.array([0.3, -0.2, 0.7])
+    v = np.tile(v0, (m.nv, 1))
+    d1, v1, _dv, st = fem.implicit_step(np.zeros((m.nv, 3)), v, dt, g=g, tol=1e-15, maxit=500,
+                                        alpha=alpha, beta=beta)
+    want = (v0 + dt * g) / (1.0 + dt * alpha)
+    assert st.status == oracle.OK
+    assert np.max(np.abs(v1 - want)) <= 1e-12 * np.abs(want).max()
+    assert np.max(np.abs(d1 - dt * v1)) <= 1e-18
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("at_rest", [True, False])
+def test_damped_step_is_modal_damped_oscillator(model, at_rest):
+    # In the M-orthonormal eigenbasis of the free block (-K phi = lam M phi) each mode is a
+    # damped oscillator with Rayleigh coefficient alpha + beta lam; one linearised backward-Euler
+    # step gives c' = (c + dt f_i) / (1 + dt (alpha + beta lam) + dt^2 lam), f_i = phi_i . (f + M g)
+    import scipy.linalg
+    m = mg.jitter(mg.kuhn_cube(2), 0.03, seed=12)
+    fem = _fem(model, m, E=2e5, nu=0.35)
+    rng = _rng(21)
+    d = np.zeros((m.nv, 3)) if at_rest else mg.perturbed_state(m, 0.01, seed=13)
+    v = 0.2 * rng.standard_normal((m.nv, 3))
+    v[m.pinned == 1] = 0.0
+    dt, alpha, beta = 1e-2, 2.5, 4e-3
+    g = np.array([0.0, 0.3, -9.81])
+    free = np.repeat(m.pinned == 0, 3)
+    K = _dense_K(fem, d)
+    Kff = K[np.ix_(free, free)]
+    Mff = np.repeat(fem.mass, 3)[free]
+    lam, Phi = scipy.linalg.eigh(-0.5 * (Kff + Kff.T), np.diag(Mff))
+    assert lam.min() > 0.0
+    f = (fem.forces(d) + fem.mass[:, None] * g).ravel()[free]
+    c = Phi.T @ (Mff * v.ravel()[free])     # modal velocities
+    fi = Phi.T @ f                           # modal forces
+    c1 = (c + dt * fi) / (1.0 + dt * (alpha + beta * lam) + dt * dt * lam)
+    want = (Phi @ c1).reshape(-1, 3)
+    _d1, v1, _dv, st = fem.implicit_step(d, v, dt, g=g, tol=1e-15, maxit=2000, alpha=alpha, beta=beta)
+    got = v1.ravel()[free].reshape(-1, 3)
+    assert st.status == oracle.OK
+    assert np.max(np.abs(got - want)) <= 1e-10 * np.abs(want).max()
+    # the undamped step is the alpha = beta = 0 case of the same modal formula
+    c0 = (c + dt * fi) / (1.0 + dt * dt * lam)
+    _d1, v0, _dv, _ = fem.implicit_step(d, v, dt, g=g, tol=1e-15, maxit=2000)
+    assert np.max(np.abs(v0.ravel()[free] - Phi @ c0)) <= 1e-10 * np.abs(Phi @ c0).max()
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_damped_step_vjp_fd(model):
+    m = mg.jitter(mg.kuhn_cube(2), 0.02, seed=6)
+    rng = _rng(17)
+    E = 1e5 * np.exp(0.3 * rng.standard_normal(m.nt))
+    fem = oracle.FEM.create(model, m.X, m.tets, E, 0.3, pinned=m.pinned)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    v = 0.05 * mg.direction(m, 11)
+    dt, tol, alpha, beta = 1e-3, 1e-14, 3.0, 2e-3
+    gx = rng.standard_normal((m.nv, 3))
+    gv = rng.standard_normal((m.nv, 3))
+
+    def J(dd, vv, EE):
+        f2 = oracle.FEM.create(model, m.X, m.tets, EE, 0.3, pinned=m.pinned)
+        d1, v1, _dv, _ = f2.implicit_step(dd, vv, dt, tol=tol, maxit=5000, alpha=alpha, beta=beta)
+        return np.sum(gx * d1) + np.sum(gv * v1), v1
+
+    _L0, v1 = J(d, v, E)
+    d_bar, v_bar, E_bar, _st = fem.step_vjp(d, v1, gx, gv, dt, tol=tol, maxit=5000, alpha=alpha, beta=beta)
+    eps = 1e-6
+    a = rng.standard_normal((m.nv, 3))
+    fd = (J(d + eps * a, v, E)[0] - J(d - eps * a, v, E)[0]) / (2 * eps)
+    assert np.sum(d_bar * a) == pytest.approx(fd, rel=1e-6)
+    fd = (J(d, v + eps * a, E)[0] - J(d, v - eps * a, E)[0]) / (2 * eps)
+    assert np.sum(v_bar * a) == pytest.approx(fd, rel=1e-6)
+    for t in [0, 7, 31]:
+        dE = np.zeros(m.nt)
+        dE[t] = 1e-6 * E[t]
+        fd = (J(d, v, E + dE)[0] - J(d, v, E - dE)[0]) / (2 * dE[t])
+        assert E_bar[t] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(E_bar).max())
+
+
+# --------------------------------------------------------------------------
 # adjoint
 # --------------------------------------------------------------------------
 
