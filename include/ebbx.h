@@ -277,6 +277,8 @@ typedef struct {
     double tol;       /* stop when ||r|| <= tol ||Pi b||; 0 runs exactly maxit iterations */
     int32_t maxit;    /* iteration cap, >= 0 */
     int32_t precond;  /* EBBX_PRECOND_* */
+    double alpha;     /* Rayleigh mass damping, >= 0 (0: none) */
+    double beta;      /* Rayleigh stiffness damping, >= 0 (0: none) */
 } ebbx_step_params;
 
 /* Solver report, written to device memory by ebbx_implicit_step. */
@@ -287,8 +289,13 @@ typedef struct {
     int64_t n_inverted;   /* NH tets with J <= 0 at d_n */
 } ebbx_step_stats;
 
-/* One linearised backward-Euler step (Vega workload; Performance Evaluation):
- *   A = M - dt^2 K(d),  b = dt (f(d) + M g + dt K(d) v),
+/* One linearised backward-Euler step (Vega workload; Performance Evaluation:
+ * each step computes the elastic forces, the stiffness and damping), with
+ * Rayleigh damping D = alpha M - beta K(d) (K = df/dx, so -K is the
+ * positive stiffness):
+ *   A = (1 + dt alpha) M - (dt^2 + dt beta) K(d),
+ *   b = dt (f(d) + M g - alpha M v + (dt + beta) K(d) v)
+ * (alpha = beta = 0: A = M - dt^2 K, b = dt (f + M g + dt K v)),
  *   Pi zeroes pinned rows; masked PCG from dv = 0 on A dv = Pi b with
  *   alpha = r^T z / p^T A p, beta = r_new^T z_new / r^T z, z = D^-1 r (Jacobi)
  *   or z = r; stop when ||r|| <= tol ||Pi b|| or after maxit iterations;
@@ -338,10 +345,10 @@ ebbx_status ebbx_fem_set_material(ebbx_fem fem, const double *E_tet_dev, const d
 /* Vector-Jacobian product of one ebbx_implicit_step taken from (d_n, v_n) to
  * (d_{n+1}, v_{n+1}).  Given gx = dL/dd_{n+1} and gv = dL/dv_{n+1}:
  *   g^ = gv + dt gx;  solve A w = Pi g^ with the step's masked PCG
- *   (A = M - dt^2 K(d_n), same params);
- *   d_bar = gx + dt K w + dt^2 T[v_{n+1}, w]   (= dL/dd_n, overwritten)
- *   v_bar = g^ + dt^2 K w                      (= dL/dv_n, overwritten)
- *   E_bar[t] += w_t . (dt f_t + dt^2 K_t v_{n+1}) / E_t   (nullable)
+ *   (A = (1 + dt alpha) M - ck K(d_n), ck = dt^2 + dt beta, same params);
+ *   d_bar = gx + dt K w + ck T[v_{n+1}, w]        (= dL/dd_n, overwritten)
+ *   v_bar = g^ + ck K w - dt alpha M w            (= dL/dv_n, overwritten)
+ *   E_bar[t] += w_t . (dt f_t + ck K_t v_{n+1}) / E_t   (nullable)
  * stats_dev (nullable) receives the adjoint solve's report.  Inputs must not
  * alias outputs (EBBX_E_PHASE). */
 ebbx_status ebbx_implicit_step_vjp(ebbx_fem fem, const double *d_n, const double *v_np1,

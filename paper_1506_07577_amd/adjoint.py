@@ -37,6 +37,8 @@ class Simulation:
     g: Sequence[float] = (0.0, 0.0, -9.81)
     precond: int = ebbx.PRECOND_JACOBI
     check_status: bool = True
+    alpha: float = 0.0   # Rayleigh damping D = alpha M - beta K
+    beta: float = 0.0
 
 
 class SolverError(RuntimeError):
@@ -57,7 +59,8 @@ def _check_stats(stats: list, what: str):
 
 
 def _step(sim: Simulation, d, v, stats):
-    st = sim.fem.implicit_step(d, v, sim.dt, g=sim.g, tol=sim.tol, maxit=sim.maxit, precond=sim.precond)
+    st = sim.fem.implicit_step(d, v, sim.dt, g=sim.g, tol=sim.tol, maxit=sim.maxit, precond=sim.precond,
+                               alpha=sim.alpha, beta=sim.beta)
     if stats is not None:
         stats.append(st)
 
@@ -114,7 +117,8 @@ class _Trajectory(torch.autograd.Function):
                 d_n = states[n - s0][0]
                 v_np1 = v_next
                 d_bar, v_bar, st = fem.step_vjp(d_n, v_np1, gx, gv, sim.dt, tol=sim.tol, maxit=sim.maxit,
-                                                precond=sim.precond, E_bar=E_bar, g=sim.g)
+                                                precond=sim.precond, E_bar=E_bar, g=sim.g, alpha=sim.alpha,
+                                                beta=sim.beta)
                 if stats is not None:
                     stats.append(st)
                 gx, gv = d_bar, v_bar

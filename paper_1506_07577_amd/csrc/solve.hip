@@ -130,13 +130,16 @@ __global__ void k_step_begin(CGState *st, int nm, SolveCtl *ctl, unsigned long l
     }
 }
 
-// b = dt (f + M g + dt K v); diag = M - dt^2 Kdiag (1 on pinned rows); r = Pi b;
-// z = D^-1 r; p = z; x = 0; chunk partials (r.z, r.r)
-// mode 0 (step): b = dt (f + M g + dt y), with f = f(d_n) and y = K(d_n) v_n;
+// diag = cm M - ck Kdiag (1 on pinned rows); r = Pi b; z = D^-1 r; p = z; x = 0;
+// chunk partials (r.z, r.r), where A = cm M - ck K with cm = 1 + dt alpha and
+// ck = dt^2 + dt beta (Rayleigh damping D = alpha M - beta K)
+// mode 0 (step): b = dt (f + M g - alpha M v_n + (dt + beta) y), with f = f(d_n)
+// and y = K(d_n) v_n;
 // mode 1 (adjoint solve): b = f, the right-hand side placed in f beforehand.
 __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
-                                                 double dt, double gx, double gy, double gz, int precond, int mode,
-                                                 Chunks ch, double *part) {
+                                                 double dt, double gx, double gy, double gz, double alpha, double beta,
+                                                 int precond, int mode, Chunks ch, double *part) {
+    const double cm = 1.0 + dt * alpha, ck = dt * dt + dt * beta;
     __shared__ double s4[4];
     const int c = blockIdx.x;
     const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
@@ -148,8 +151,8 @@ __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, 
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
-            const double b = mode ? w.f[i] : dt * (w.f[i] + m * g[k] + dt * w.y[i]);
-            const double dg = pin ? 1.0 : (precond ? m - dt * dt * w.diag[i] : 1.0);
+            const double b = mode ? w.f[i] : dt * (w.f[i] + m * g[k] - alpha * m * w.vn[i] + (dt + beta) * w.y[i]);
+            const double dg = pin ? 1.0 : (precond ? cm * m - ck * w.diag[i] : 1.0);
             const double r = pin ? 0.0 : b;
             const double z = r / dg;
             w.diag[i] = dg;
@@ -228,9 +231,10 @@ __device__ __forceinline__ void finished(const HaloView &h, const double *y, int
     o[2] = a2;
 }
 
-// q = Pi (M p - dt^2 y); chunk partial p.q (y finished here if the element map left it in the halo)
+// q = Pi (cm M p - ck y); chunk partial p.q (y finished here if the element map left it in the halo)
 __global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
-                                              double dt, const CGState *st, Chunks ch, HaloView hv, double *part) {
+                                              double cm, double ck, const CGState *st, Chunks ch, HaloView hv,
+                                              double *part) {
     __shared__ double s4[4];
     const int c = blockIdx.x;
     if (st[ch.mesh[c]].done) return;   // uniform over the block
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, con
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
             const double p = w.p[i];
-            const double q = pin ? 0.0 : m * p - dt * dt * y[k];
+            const double q = pin ? 0.0 : cm * m * p - ck * y[k];
             w.q[i] = q;
             pq += p * q;
         }
@@ -484,11 +488,11 @@ __global__ void k_vjp_prep(const double *d, const double *gx, const double *gv, 
     }
 }
 
-// adjoint: d_bar = gx + dt K w + dt^2 T[v', w];  v_bar = g^ + dt^2 K w
-// (K w in y, T[v', w] in q, g^ in f); stats of each mesh's adjoint solve
-__global__ __launch_bounds__(VT) void k_vjp_end(StepVec w, const double *gx, double dt, int64_t nv, const CGState *st,
-                                                Chunks ch, double tol, double *d_bar, double *v_bar,
-                                                ebbx_step_stats *stats) {
+// adjoint: d_bar = gx + dt K w + ck T[v', w];  v_bar = g^ + ck K w - dt alpha M w
+// (K w in y, T[v', w] in q, g^ in f, w in x); stats of each mesh's adjoint solve
+__global__ __launch_bounds__(VT) void k_vjp_end(StepVec w, const double *gx, const double *mass, double dt, double ck,
+                                                double dt_alpha, int64_t nv, const CGState *st, Chunks ch, double tol,
+                                                double *d_bar, double *v_bar, ebbx_step_stats *stats) {
     const int c = blockIdx.x, m = ch.mesh[c];
     const int64_t j = (int64_t)ch.lo[c] + threadIdx.x;
     if (j < ch.hi[c])
@@ -496,8 +500,8 @@ __global__ __launch_bounds__(VT) void k_vjp_end(StepVec w, const double *gx, dou
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + j;
             const double kw = w.y[i];
-            d_bar[i] = gx[i] + dt * kw + dt * dt * w.q[i];
-            v_bar[i] = w.f[i] + dt * dt * kw;
+            d_bar[i] = gx[i] + dt * kw + ck * w.q[i];
+            v_bar[i] = w.f[i] + ck * kw - dt_alpha * mass[j] * w.x[i];
         }
     if (stats && c == ch.cptr[m] && threadIdx.x == 0) write_stats(st[m], tol, stats + m);
 }
@@ -550,7 +554,7 @@ struct ebbx_fem_s::Step {
     bool valid = false;   // graphs match the parameters below
     bool fused = true;    // one-kernel alpha and beta (every mesh has at most FUSE_CHUNKS chunks)
     // parameters baked into the graphs
-    double dt = -1, g[3] = {0, 0, 0}, tol = -1;
+    double dt = -1, g[3] = {0, 0, 0}, tol = -1, alpha = -1, beta = -1;
     int maxit = -1, precond = -1, strategy = -1, block = -1;
     int *h_done = nullptr;   // pinned host flag for convergence checks
     void drop_graphs() {
@@ -598,6 +602,7 @@ hipGraphExec_t capture_end(hipStream_t cap, hipGraph_t *g) {
 void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     auto &S = *F->step;
     const bool same = S.dt == p.dt && !std::memcmp(S.g, p.g, sizeof S.g) && S.tol == p.tol && S.maxit == p.maxit &&
+                      S.alpha == p.alpha && S.beta == p.beta &&
                       S.precond == p.precond && S.strategy == F->strategy && S.block == F->block && S.valid;
     if (!same) S.drop_graphs();
     if (S.pre[mode]) return;
@@ -617,7 +622,7 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     }
     if (p.precond == EBBX_PRECOND_JACOBI) elem_launch(F, OP_DIAG, S.w.dn, nullptr, S.w.diag, 0, cs);
     hipLaunchKernelGGL(k_step_rhs, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(), nv,
-                       p.dt, p.g[0], p.g[1], p.g[2], p.precond, mode, S.ch, part);
+                       p.dt, p.g[0], p.g[1], p.g[2], p.alpha, p.beta, p.precond, mode, S.ch, part);
     hipLaunchKernelGGL(k_step_init, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch,
                        (const unsigned long long *)n_inv, ctl);
     // chunks of CG iterations; every kernel is predicated on its mesh's done flag,
@@ -634,12 +639,13 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     // K p: a block-strategy element map leaves its shared vertices in the halo and
     // k_cg_Ap finishes them as it reads y (one launch and one y round trip fewer)
     const HaloView hv = elem_halo_view(F);
+    const double cm = 1.0 + p.dt * p.alpha, ck = p.dt * p.dt + p.dt * p.beta;
     auto iterations = [&](int count) {
         for (int it = 0; it < count && it < p.maxit; ++it) {
             elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &ctl->all_done, nullptr,
                         nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr);
             hipLaunchKernelGGL(k_cg_Ap, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
-                               nv, p.dt, (const CGState *)st, S.ch, hv, part);
+                               nv, cm, ck, (const CGState *)st, S.ch, hv, part);
             if (S.fused) {
                 const int par = it & 1;   // chunks after the first start at even iterations
                 hipLaunchKernelGGL(k_cg_update_f, dim3(nch), dim3(VT), 0, cs, S.w, nv, st, S.ch, part, par, ctl);
@@ -669,6 +675,8 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     S.dt = p.dt;
     std::memcpy(S.g, p.g, sizeof S.g);
     S.tol = p.tol;
+    S.alpha = p.alpha;
+    S.beta = p.beta;
     S.maxit = p.maxit;
     S.precond = p.precond;
     S.strategy = F->strategy;
@@ -681,6 +689,8 @@ void check_step_params(const ebbx_step_params *params) {
     if (!(p.dt > 0.0)) fail(EBBX_E_ARG, "dt must be > 0");
     if (p.maxit < 0) fail(EBBX_E_ARG, "maxit must be >= 0");
     if (!(p.tol >= 0.0)) fail(EBBX_E_ARG, "tol must be >= 0");
+    if (!(p.alpha >= 0.0) || !(p.beta >= 0.0) || !std::isfinite(p.alpha) || !std::isfinite(p.beta))
+        fail(EBBX_E_ARG, "damping coefficients alpha and beta must be finite and >= 0");
     if (p.precond != EBBX_PRECOND_NONE && p.precond != EBBX_PRECOND_JACOBI) fail(EBBX_E_ARG, "bad precond");
 }
 
@@ -808,14 +818,16 @@ extern "C" ebbx_status ebbx_implicit_step_vjp(ebbx_fem fem, const double *d_n, c
         hipLaunchKernelGGL(k_vjp_prep, dim3(grid_for(3 * nv)), dim3(VT), 0, s, d_n, gx, gv, p.dt, S.w, 3 * nv);
         HIPCHK(hipGetLastError());
     }
-    // A w = Pi (gv + dt gx), with A = M - dt^2 K(d_n); w ends in x
+    // A w = Pi (gv + dt gx), with A = (1 + dt alpha) M - (dt^2 + dt beta) K(d_n); w ends in x
     run_solve(F, p, 1, s);
     elem_launch(F, OP_KMUL, S.w.dn, S.w.x, S.w.y, 0, s);
     elem_launch(F, OP_TMUL, S.w.dn, v_np1, S.w.q, 0, s, nullptr, S.w.x);
-    hipLaunchKernelGGL(k_vjp_end, dim3(S.nch), dim3(VT), 0, s, S.w, gx, p.dt, nv,
-                       (const CGState *)S.state.as<CGState>(), S.ch, p.tol, d_bar, v_bar, stats_dev);
+    const double ck = p.dt * p.dt + p.dt * p.beta;
+    hipLaunchKernelGGL(k_vjp_end, dim3(S.nch), dim3(VT), 0, s, S.w, gx, F->mass.as<double>(), p.dt, ck,
+                       p.dt * p.alpha, nv, (const CGState *)S.state.as<CGState>(), S.ch, p.tol, d_bar, v_bar,
+                       stats_dev);
     HIPCHK(hipGetLastError());
-    if (E_bar) elem_egrad(F, S.w.dn, v_np1, S.w.x, p.dt, p.dt * p.dt, E_bar, s);
+    if (E_bar) elem_egrad(F, S.w.dn, v_np1, S.w.x, p.dt, ck, E_bar, s);
     EBBX_API_END
 }
 

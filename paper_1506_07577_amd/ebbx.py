@@ -42,7 +42,7 @@ class FemParams(C.Structure):
 
 class StepParams(C.Structure):
     _fields_ = [("dt", C.c_double), ("g", C.c_double * 3), ("tol", C.c_double), ("maxit", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("alpha", C.c_double), ("beta", C.c_double)]
 
 
 class StepStats(C.Structure):
@@ -392,8 +392,9 @@ class Fem:
                                            _stream(stream)))
 
     def step_vjp(self, d_n, v_np1, gx, gv, dt, tol=1e-10, maxit=1000, precond=PRECOND_JACOBI,
-                 E_bar=None, g=(0.0, 0.0, -9.81), stats=None, stream=None):
-        """Returns (d_bar, v_bar, stats); accumulates dL/dE into E_bar if given."""
+                 E_bar=None, g=(0.0, 0.0, -9.81), stats=None, stream=None, alpha=0.0, beta=0.0):
+        """Returns (d_bar, v_bar, stats); accumulates dL/dE into E_bar if given.
+        alpha, beta: the Rayleigh damping of the step being differentiated."""
         for t, n in ((d_n, "d_n"), (v_np1, "v_np1"), (gx, "gx"), (gv, "gv")):
             self._vec(t, n)
         d_bar = torch.empty_like(d_n)
@@ -402,20 +403,23 @@ class Fem:
             stats = torch.zeros(3, dtype=torch.int64, device=d_n.device)
         if E_bar is not None:
             _dev(E_bar, torch.float64, "E_bar")
-        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond))
+        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond), float(alpha),
+                       float(beta))
         _check(lib().ebbx_implicit_step_vjp(self.h, _ptr(d_n), _ptr(v_np1), C.byref(p), _ptr(gx), _ptr(gv),
                                             _ptr(d_bar), _ptr(v_bar), _ptr(E_bar), _ptr(stats),
                                             _stream(stream)))
         return d_bar, v_bar, stats
 
     def implicit_step(self, d, v, dt, g=(0.0, 0.0, -9.81), tol=0.0, maxit=100,
-                      precond=PRECOND_JACOBI, stats=None, stream=None):
-        """Advance (d, v) in place; returns the device stats tensor (24 bytes)."""
+                      precond=PRECOND_JACOBI, stats=None, stream=None, alpha=0.0, beta=0.0):
+        """Advance (d, v) in place; returns the device stats tensor (24 bytes).
+        alpha, beta: Rayleigh damping D = alpha M - beta K (K = df/dx)."""
         self._vec(d, "d")
         self._vec(v, "v")
         if stats is None:
             stats = torch.zeros(3, dtype=torch.int64, device=d.device)
-        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond))
+        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond), float(alpha),
+                       float(beta))
         _check(lib().ebbx_implicit_step(self.h, _ptr(d), _ptr(v), C.byref(p), _ptr(stats),
                                         _stream(stream)))
         return stats
@@ -440,13 +444,14 @@ class Batch:
         self.fem = Fem._borrowed(hf, tets, verts, model, elem_prec)
 
     def implicit_step(self, d, v, dt, g=(0.0, 0.0, -9.81), tol=1e-8, maxit=1000, precond=PRECOND_JACOBI,
-                      stats=None, stream=None):
+                      stats=None, stream=None, alpha=0.0, beta=0.0):
         """Advance every mesh in place; returns the (nm, 3) int64 device stats tensor."""
         self.fem._vec(d, "d")
         self.fem._vec(v, "v")
         if stats is None:
             stats = torch.zeros(self.nm, 3, dtype=torch.int64, device=d.device)
-        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond))
+        p = StepParams(float(dt), (C.c_double * 3)(*g), float(tol), int(maxit), int(precond), float(alpha),
+                       float(beta))
         _check(lib().ebbx_batch_implicit_step(self.h, _ptr(d), _ptr(v), C.byref(p), _ptr(stats), _stream(stream)))
         return stats
 
@@ -558,5 +563,21 @@ class FemMesh:
         if self.vperm is not None:
             out = a.copy()
             out[self.vperm.cpu().numpy()] = a
+            a = out
+        return a
+
+    def tet_to_dev(self, a):
+        """(nt,) per-tet array in the caller's tet order -> FP64 device tensor in library order."""
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if self.tperm is not None:
+            t = t[self.tperm.cpu().long()]
+        return t.contiguous().cuda()
+
+    def tet_from_dev(self, t):
+        """(nt,) device tensor in library order -> numpy in the caller's tet order."""
+        a = t.detach().cpu().numpy()
+        if self.tperm is not None:
+            out = a.copy()
+            out[self.tperm.cpu().numpy()] = a
             a = out
         return a
