@@ -68,11 +68,14 @@ def _load():
     lib.orc_implicit_step.argtypes = base + [P, P, D, P, D, D, D, I32, I32, P, P, P, P]
     lib.orc_step_vjp.argtypes = base + [P, P, P, D, D, D, D, I32, I32, P, P, P, P, P, P, P, P]
     lib.orc_group_by.argtypes = [I64, I64, P, P, P]
+    lib.orc_edges.argtypes = [I64, I64, P, P, P, I64, P]
+    lib.orc_assemble.argtypes = base + [P, P, P, P]
+    lib.orc_spmv.argtypes = [I64, P, P, P, P, P]
     lib.orc_morton.argtypes = [I64, I64, P, P, P, P, P]
     for f in ("orc_precompute", "orc_stress", "orc_dstress", "orc_d2stress",
               "orc_energy_density", "orc_forces", "orc_kmul", "orc_tmul", "orc_energy",
               "orc_jacobi_diag", "orc_implicit_step", "orc_step_vjp", "orc_group_by",
-              "orc_morton"):
+              "orc_morton", "orc_edges", "orc_assemble", "orc_spmv"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -138,6 +141,30 @@ def group_by(nv: int, tets: np.ndarray):
     inc = np.zeros(4 * nt, dtype=np.int32)
     _chk(_load().orc_group_by(nv, nt, _p(tets), _p(row_ptr), _p(inc)), "group_by")
     return row_ptr, inc
+
+
+def edges(nv: int, tets: np.ndarray):
+    """Directed edges grouped by tail: (row_ptr (nv+1) int64, col int32)."""
+    tets = np.ascontiguousarray(tets, dtype=np.int32)
+    nt = tets.shape[0]
+    row_ptr = np.zeros(nv + 1, dtype=np.int64)
+    cap = 16 * nt
+    col = np.zeros(max(cap, 1), dtype=np.int32)
+    n = C.c_int64()
+    _chk(_load().orc_edges(nv, nt, _p(tets), _p(row_ptr), _p(col), cap, C.byref(n)), "edges")
+    return row_ptr, col[: n.value].copy()
+
+
+def spmv(row_ptr, col, blocks, u):
+    """y_i = sum_j K_ij u_j over the assembled blocks ((n_edges, 3, 3))."""
+    nv = len(row_ptr) - 1
+    u = _f64(u, (nv, 3))
+    y = np.zeros((nv, 3))
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    bl = _f64(blocks)
+    _chk(_load().orc_spmv(nv, _p(rp), _p(cl), _p(bl), _p(u), _p(y)), "spmv")
+    return y
 
 
 def morton(X: np.ndarray, tets: np.ndarray):
@@ -209,6 +236,15 @@ class FEM:
         y = np.zeros((self.nv, 3))
         _chk(_load().orc_kmul(*self._base(), _p(d), _p(u), _p(y)), "kmul")
         return y
+
+    def assemble(self, d, row_ptr, col):
+        """Per-edge 3x3 stiffness blocks K_ij = df_i/dd_j at d: (n_edges, 3, 3)."""
+        d = _f64(d, (self.nv, 3))
+        blocks = np.zeros((max(len(col), 1), 3, 3))
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        _chk(_load().orc_assemble(*self._base(), _p(d), _p(rp), _p(cl), _p(blocks)), "assemble")
+        return blocks[: len(col)]
 
     def tmul(self, d, a, w):
         d, a, w = (_f64(x, (self.nv, 3)) for x in (d, a, w))

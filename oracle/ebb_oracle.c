@@ -608,6 +608,97 @@ done:
     return st;
 }
 
+/* ---- assembled stiffness on edges --------------------------------------------
+ * The Vega workload keeps its stiffness matrix on the mesh edges (Developing
+ * Domain Libraries, "Example: FEM tetmesh"; Performance Evaluation): one 3x3
+ * block per ordered vertex pair that shares a tet, self-pairs included,
+ * grouped by the first (tail) vertex.  Block (i, j) is df_i/dd_j, the sum over
+ * the tets holding both vertices of that tet's corner block. */
+
+static int i64_cmp(const void *a, const void *b) {
+    const int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+int orc_edges(int64_t nv, int64_t nt, const int32_t *tets, int64_t *row_ptr, int32_t *col,
+              int64_t cap, int64_t *n_edges) {
+    int64_t *key = malloc(sizeof(int64_t) * (size_t)(16 * nt + 1));
+    if (!key) return ORC_E_ARG;
+    for (int64_t t = 0; t < nt; ++t)
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                const int32_t i = tets[4 * t + a], j = tets[4 * t + b];
+                if (i < 0 || i >= nv || j < 0 || j >= nv) { free(key); return ORC_E_ARG; }
+                key[16 * t + 4 * a + b] = (int64_t)i * nv + j;
+            }
+    qsort(key, (size_t)(16 * nt), sizeof(int64_t), i64_cmp);
+    int64_t n = 0;
+    for (int64_t v = 0; v <= nv; ++v) row_ptr[v] = 0;
+    for (int64_t k = 0; k < 16 * nt; ++k) {
+        if (k > 0 && key[k] == key[k - 1]) continue;
+        if (n < cap) col[n] = (int32_t)(key[k] % nv);
+        ++row_ptr[key[k] / nv + 1];
+        ++n;
+    }
+    for (int64_t v = 0; v < nv; ++v) row_ptr[v + 1] += row_ptr[v];
+    free(key);
+    *n_edges = n;
+    return n <= cap ? ORC_OK : ORC_E_ARG;
+}
+
+static int64_t edge_find(const int64_t *row_ptr, const int32_t *col, int32_t i, int32_t j) {
+    int64_t lo = row_ptr[i], hi = row_ptr[i + 1];
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (col[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < row_ptr[i + 1] && col[lo] == j) ? lo : -1;
+}
+
+int orc_assemble(int model, int64_t nv, int64_t nt, const int32_t *tets,
+                 const double *B, const double *V0, const double *mu, const double *lam,
+                 const double *d, const int64_t *row_ptr, const int32_t *col, double *blocks) {
+    memset(blocks, 0, sizeof(double) * (size_t)(9 * row_ptr[nv]));
+    for (int64_t t = 0; t < nt; ++t) {
+        const int32_t *tv = tets + 4 * t;
+        const double *Bt = B + 9 * t;
+        double G[9];
+        tet_grad(tv, d, Bt, G);
+        for (int b = 0; b < 4; ++b)
+            for (int k = 0; k < 3; ++k) {
+                /* unit displacement of corner b along axis k: dF = e_k (x) grad(N_b) */
+                double gb[3], dF[9], dP[9], loc[12] = {0};
+                const int32_t id[4] = {0, 1, 2, 3};
+                for (int j = 0; j < 3; ++j)
+                    gb[j] = b ? Bt[3 * (b - 1) + j] : -(Bt[j] + Bt[3 + j] + Bt[6 + j]);
+                m_zero(dF);
+                for (int j = 0; j < 3; ++j) dF[3 * k + j] = gb[j];
+                int st = orc_dstress(model, mu[t], lam[t], G, dF, dP);
+                if (st) return st;
+                tet_scatter(id, V0[t], dP, Bt, loc);   /* loc[3a + r] = df_{a,r} / dd_{b,k} */
+                for (int a = 0; a < 4; ++a) {
+                    const int64_t e = edge_find(row_ptr, col, tv[a], tv[b]);
+                    if (e < 0) return ORC_E_ARG;
+                    for (int r = 0; r < 3; ++r) blocks[9 * e + 3 * r + k] += loc[3 * a + r];
+                }
+            }
+    }
+    return ORC_OK;
+}
+
+int orc_spmv(int64_t nv, const int64_t *row_ptr, const int32_t *col, const double *blocks,
+             const double *u, double *y) {
+    for (int64_t i = 0; i < nv; ++i) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            for (int r = 0; r < 3; ++r)
+                for (int c = 0; c < 3; ++c) acc[r] += blocks[9 * e + 3 * r + c] * u[3 * (int64_t)col[e] + c];
+        for (int r = 0; r < 3; ++r) y[3 * i + r] = acc[r];
+    }
+    return ORC_OK;
+}
+
 /* ---- grouping and reordering ------------------------------------------------ */
 
 typedef struct { int64_t key; int64_t val; } kv_t;

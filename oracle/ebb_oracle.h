@@ -91,6 +91,20 @@ int orc_step_vjp(int model, int64_t nv, int64_t nt, const int32_t *tets,
                  const double *gx, const double *gv,
                  double *d_bar, double *v_bar, double *E_bar, orc_stats *stats);
 
+/* Directed edges (i, j) of the tets, self-pairs included, sorted by (i, j):
+ * row_ptr (nv+1) over tails, col (heads, capacity cap); *n_edges = count
+ * (ORC_E_ARG if it exceeds cap). */
+int orc_edges(int64_t nv, int64_t nt, const int32_t *tets, int64_t *row_ptr, int32_t *col,
+              int64_t cap, int64_t *n_edges);
+/* Assembled stiffness at displacement d: blocks[9e + 3r + c] = df_{i,r}/dd_{j,c}
+ * for edge e = (i, j), summed over the tets holding both vertices. */
+int orc_assemble(int model, int64_t nv, int64_t nt, const int32_t *tets,
+                 const double *B, const double *V0, const double *mu, const double *lam,
+                 const double *d, const int64_t *row_ptr, const int32_t *col, double *blocks);
+/* y_i = sum over edges (i, j) of K_ij u_j. */
+int orc_spmv(int64_t nv, const int64_t *row_ptr, const int32_t *col, const double *blocks,
+             const double *u, double *y);
+
 /* Grouping of the tets.v[4] key-field by vertex: CSR of incidence 4t+c,
  * rows in (t, c) order.  row_ptr: nv+1, inc: 4 nt. */
 int orc_group_by(int64_t nv, int64_t nt, const int32_t *tets, int64_t *row_ptr, int32_t *inc);

@@ -467,6 +467,71 @@ def test_pcg_breakdown_and_maxit():
 
 
 # --------------------------------------------------------------------------
+# assembled stiffness on edges (Vega keeps K on the mesh edges)
+# --------------------------------------------------------------------------
+
+def test_edges_brute_force():
+    m, _, _ = mg.scramble(mg.jitter(mg.kuhn_cube(3), 0.02, seed=2), seed=5)
+    row_ptr, col = oracle.edges(m.nv, m.tets)
+    want = sorted({(int(i), int(j)) for t in m.tets for i in t for j in t})
+    got = [(i, int(col[e])) for i in range(m.nv) for e in range(row_ptr[i], row_ptr[i + 1])]
+    assert got == want
+    # Kuhn lattice: an interior vertex has 14 neighbours plus itself
+    k = mg.kuhn_cube(3)
+    rp, _ = oracle.edges(k.nv, k.tets)
+    deg = np.diff(rp)
+    interior = np.all((k.X > 0.01) & (k.X < 0.99), axis=1)
+    assert np.all(deg[interior] == 15)
+
+
+@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("name,m", list(_meshes()))
+def test_assembled_spmv_is_matrix_free_kmul(model, name, m):
+    fem = _fem(model, m)
+    rp, col = oracle.edges(m.nv, m.tets)
+    rng = _rng(31)
+    for d in (np.zeros((m.nv, 3)), mg.perturbed_state(m, 0.05, seed=10)):
+        blocks = fem.assemble(d, rp, col)
+        for _ in range(3):
+            u = rng.standard_normal((m.nv, 3))
+            y = oracle.spmv(rp, col, blocks, u)
+            ref = fem.kmul(d, u)
+            assert np.max(np.abs(y - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_assembled_blocks_symmetric_and_translation_free(model):
+    m = mg.jitter(mg.kuhn_cube(2), 0.05, seed=8)
+    fem = _fem(model, m)
+    rp, col = oracle.edges(m.nv, m.tets)
+    blocks = fem.assemble(mg.perturbed_state(m, 0.05, seed=10), rp, col)
+    scale = np.abs(blocks).max()
+    for i in range(m.nv):
+        row = blocks[rp[i]:rp[i + 1]]
+        assert np.abs(row.sum(axis=0)).max() <= 1e-12 * scale   # K annihilates translations
+        for e in range(rp[i], rp[i + 1]):
+            j = col[e]
+            et = rp[j] + int(np.searchsorted(col[rp[j]:rp[j + 1]], i))
+            assert col[et] == i
+            assert np.abs(blocks[e] - blocks[et].T).max() <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_assembled_rest_blocks_are_linear_elasticity(model):
+    # independent textbook route: Voigt assembly of linear elasticity, read block by block
+    m = mg.jitter(mg.kuhn_cube(2), 0.05, seed=9)
+    fem = _fem(model, m, E=3e5, nu=0.33)
+    rp, col = oracle.edges(m.nv, m.tets)
+    blocks = fem.assemble(np.zeros((m.nv, 3)), rp, col)
+    Kv = _voigt_stiffness(m, 3e5, 0.33)
+    for i in range(m.nv):
+        for e in range(rp[i], rp[i + 1]):
+            j = col[e]
+            want = -Kv[3 * i:3 * i + 3, 3 * j:3 * j + 3]
+            assert np.abs(blocks[e] - want).max() <= 1e-12 * np.abs(Kv).max()
+
+
+# --------------------------------------------------------------------------
 # Rayleigh damping (Vega's step computes damping with forces and stiffness:
 # Performance Evaluation); D = alpha M - beta K with K = df/dx
 # --------------------------------------------------------------------------
