@@ -310,6 +310,41 @@ typedef struct {
 ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
                                ebbx_step_stats *stats_dev, ebbx_stream stream);
 
+/* ---- stiffness assembled on edges ---------------------------------------- */
+
+/* The Vega workload keeps its stiffness matrix on the mesh edges (Developing
+ * Domain Libraries, "Example: FEM tetmesh"; Performance Evaluation).  The
+ * edges relation of a domain holds every ordered vertex pair (i, j) that
+ * shares a tet, i == j included, grouped by the tail i and sorted by the head
+ * j: row_ptr (nv + 1 int32) and col (n_edges int32), a block-CSR pattern.  It
+ * is built on the host from the grouping on first use (synchronous), once per
+ * domain, with per-edge lists of the (tet, corner, corner) blocks that sum
+ * into it.
+ *
+ * ebbx_fem_assemble: K(d) into one 3x3 block per edge, block(i, j)[r][c] =
+ * df_{i,r}/dd_{j,c}, the sum over the tets holding i and j, in ascending tet
+ * order, of the tet's corner block.  Each tet's 12 x 12 stiffness is computed
+ * in FP64 from the same dP as ebbx_fem_Kmul (columns: unit corner
+ * displacements); the blocks are stored at the domain's element precision,
+ * nine columns of n_edges values.  The library owns a per-tet scratch of
+ * 144 FP64 values per tet (about 1.2 KB/tet) and the blocks.  NH tets with
+ * J <= 0 are counted as by ebbx_fem_forces.  Enqueued on stream (after the
+ * synchronous first build). */
+ebbx_status ebbx_fem_assemble(ebbx_fem fem, const double *d, ebbx_stream stream);
+
+/* y (+)= K u with the blocks of the last ebbx_fem_assemble; FP64 (3, nv)
+ * vectors, FP64 accumulation, each row summed in a fixed order.
+ * EBBX_E_STATE before any assembly, EBBX_E_PHASE if y aliases u. */
+ebbx_status ebbx_fem_spmv(ebbx_fem fem, const double *u, double *y, int32_t accumulate, ebbx_stream stream);
+
+/* Number of directed edges (builds the edges relation if needed). */
+ebbx_status ebbx_fem_edge_count(ebbx_fem fem, int64_t *n_edges);
+
+/* Copies into caller device buffers (each nullable): row_ptr (nv + 1 int32),
+ * col (n_edges int32), blocks (9, n_edges) FP64, column q = 3 r + c of every
+ * block (EBBX_E_STATE for blocks before any assembly).  Enqueued on stream. */
+ebbx_status ebbx_fem_edges_get(ebbx_fem fem, int32_t *row_ptr, int32_t *col, double *blocks, ebbx_stream stream);
+
 /* ---- adjoint (vector-Jacobian products) ---------------------------------- */
 
 /* T[a, w] = grad_x (w^T K(x) a) at displacement d: per tet the second

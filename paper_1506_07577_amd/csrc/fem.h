@@ -86,6 +86,13 @@ void fill_f64(double *p, int64_t n, double v, hipStream_t s);
 void build_blocks(ebbx_fem_s *F, int32_t tets_per_block, hipStream_t s);
 // Build the vertex-owned block tables of the OWNER strategy.
 void build_owner(ebbx_fem_s *F, int32_t verts_per_block, hipStream_t s);
+// Assembled stiffness on edges (assemble.hip): the edges relation (once per
+// domain, synchronous), K(d) into the edge blocks, y (+)= K u over them, and
+// copies of the relation and the blocks (FP64) into caller buffers.
+void build_edges(ebbx_fem_s *F, hipStream_t s);
+void assemble_stiffness(ebbx_fem_s *F, const double *d, hipStream_t s);
+void assembled_spmv(ebbx_fem_s *F, const double *u, double *y, int accumulate, hipStream_t s);
+void edges_copy(ebbx_fem_s *F, int32_t *row, int32_t *col, double *blocks, hipStream_t s);
 
 // FEM handle registry (fem.hip).
 ebbx_fem_s *check_fem(ebbx_fem f);
@@ -145,6 +152,10 @@ struct ebbx_fem_s {
     int32_t own_maxinc = 0;    // most owned incidences of one block
     int64_t own_ntb = 0;       // (block, tet) pairs over all blocks
     ebbx::DevBuf own_tptr, own_meta, own_gptr, own_ghost;
+    // assembled stiffness: directed edges grouped by tail (built on first use)
+    int64_t n_edges = -1;      // -1: not built
+    bool assembled = false;    // e_blocks holds K(d) of an ebbx_fem_assemble call
+    ebbx::DevBuf e_row, e_col, e_gptr, e_gent, e_blocks, e_ke;
 
     // implicit-step state (allocated on first step)
     struct Step;

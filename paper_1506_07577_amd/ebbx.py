@@ -122,6 +122,10 @@ def lib():
         "ebbx_batch_destroy": ([P], I32_),
         "ebbx_batch_fem": ([P, C.POINTER(P)], I32_),
         "ebbx_batch_implicit_step": ([P, P, P, C.POINTER(StepParams), P, P], I32_),
+        "ebbx_fem_assemble": ([P, P, P], I32_),
+        "ebbx_fem_spmv": ([P, P, P, I32_, P], I32_),
+        "ebbx_fem_edge_count": ([P, C.POINTER(I64_)], I32_),
+        "ebbx_fem_edges_get": ([P, P, P, P, P], I32_),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -316,6 +320,34 @@ class Fem:
         _check(lib().ebbx_fem_Kmul(self.h, _ptr(d), _ptr(u), _ptr(y), int(bool(accumulate)),
                                    _stream(stream)))
         return y
+
+    def assemble(self, d, stream=None):
+        """Assemble K(d) into the per-edge 3x3 blocks (the edges relation is built on first use)."""
+        self._vec(d, "d")
+        _check(lib().ebbx_fem_assemble(self.h, _ptr(d), _stream(stream)))
+
+    def spmv(self, u, y=None, accumulate=False, stream=None):
+        """y (+)= K u with the blocks of the last assemble()."""
+        self._vec(u, "u")
+        if y is None:
+            y = torch.empty_like(u)
+        self._vec(y, "y")
+        _check(lib().ebbx_fem_spmv(self.h, _ptr(u), _ptr(y), int(bool(accumulate)), _stream(stream)))
+        return y
+
+    def edge_count(self):
+        n = C.c_int64()
+        _check(lib().ebbx_fem_edge_count(self.h, C.byref(n)))
+        return n.value
+
+    def edges(self, blocks=True, stream=None):
+        """(row_ptr (nv+1) int32, col (n_edges) int32, blocks (9, n_edges) FP64 or None), library order."""
+        n = self.edge_count()
+        row = torch.empty(self.nv + 1, dtype=torch.int32, device="cuda")
+        col = torch.empty(max(n, 1), dtype=torch.int32, device="cuda")
+        blk = torch.empty(9, max(n, 1), dtype=torch.float64, device="cuda") if blocks else None
+        _check(lib().ebbx_fem_edges_get(self.h, _ptr(row), _ptr(col), _ptr(blk), _stream(stream)))
+        return row, col[:n], (blk[:, :n] if blk is not None else None)
 
     def energy(self, d, stream=None):
         self._vec(d, "d")
