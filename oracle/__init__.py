@@ -71,11 +71,17 @@ def _load():
     lib.orc_edges.argtypes = [I64, I64, P, P, P, I64, P]
     lib.orc_assemble.argtypes = base + [P, P, P, P]
     lib.orc_spmv.argtypes = [I64, P, P, P, P, P]
+    lib.orc_spring_rest.argtypes = [I64, P, P, P, P]
+    lib.orc_spring_forces.argtypes = [I64, I64, P, P, P, D, P, P]
+    lib.orc_spring_apply.argtypes = [I64, P, D, P, P, P]
+    lib.orc_kinetic_energy.argtypes = [I64, P, P]
+    lib.orc_kinetic_energy.restype = D
     lib.orc_morton.argtypes = [I64, I64, P, P, P, P, P]
     for f in ("orc_precompute", "orc_stress", "orc_dstress", "orc_d2stress",
               "orc_energy_density", "orc_forces", "orc_kmul", "orc_tmul", "orc_energy",
               "orc_jacobi_diag", "orc_implicit_step", "orc_step_vjp", "orc_group_by",
-              "orc_morton", "orc_edges", "orc_assemble", "orc_spmv"):
+              "orc_morton", "orc_edges", "orc_assemble", "orc_spmv", "orc_spring_rest",
+              "orc_spring_forces", "orc_spring_apply"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -165,6 +171,41 @@ def spmv(row_ptr, col, blocks, u):
     bl = _f64(blocks)
     _chk(_load().orc_spmv(nv, _p(rp), _p(cl), _p(bl), _p(u), _p(y)), "spmv")
     return y
+
+
+class Springs:
+    """Spring-mass workload on directed edges (tail, head): rest lengths from X."""
+
+    def __init__(self, X, tail, head, mass, K):
+        self.X = _f64(X)
+        self.nv = self.X.shape[0]
+        self.tail = np.ascontiguousarray(tail, dtype=np.int32)
+        self.head = np.ascontiguousarray(head, dtype=np.int32)
+        self.ne = len(self.tail)
+        self.mass = _f64(mass)
+        self.K = float(K)
+        self.rest = np.zeros(max(self.ne, 1))
+        _chk(_load().orc_spring_rest(self.ne, _p(self.tail), _p(self.head), _p(self.X), _p(self.rest)),
+             "spring_rest")
+
+    def forces(self, q):
+        q = _f64(q, (self.nv, 3))
+        f = np.zeros((self.nv, 3))
+        _chk(_load().orc_spring_forces(self.nv, self.ne, _p(self.tail), _p(self.head), _p(self.rest), self.K,
+                                       _p(q), _p(f)), "spring_forces")
+        return f
+
+    def step(self, q, qd, dt):
+        """One step (forces, then the exclusive update); returns (q', qd')."""
+        q = _f64(q, (self.nv, 3)).copy()
+        qd = _f64(qd, (self.nv, 3)).copy()
+        f = self.forces(q)
+        _chk(_load().orc_spring_apply(self.nv, _p(self.mass), float(dt), _p(q), _p(qd), _p(f)), "spring_apply")
+        return q, qd
+
+    def kinetic_energy(self, qd):
+        qd = _f64(qd, (self.nv, 3))
+        return _load().orc_kinetic_energy(self.nv, _p(self.mass), _p(qd))
 
 
 def morton(X: np.ndarray, tets: np.ndarray):

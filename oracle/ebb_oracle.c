@@ -699,6 +699,66 @@ int orc_spmv(int64_t nv, const int64_t *row_ptr, const int32_t *col, const doubl
     return ORC_OK;
 }
 
+/* ---- spring-mass workload ---------------------------------------------------
+ * The introductory example of the paper (Ebb by example: a spring-mass
+ * simulation on the edges of a tet mesh): a spring on every directed edge,
+ * its rest length from the rest positions; each vertex sums the springs of
+ * the edges leaving it (a query loop over the edges grouped by tail, a +=
+ * reduction into the vertex force), then an exclusive per-vertex update
+ * integrates and clears the force; the kinetic energy is a global +=.
+ * Springs restore: an edge (v -> h) adds K (dq - L dq/|dq|), dq = q_h - q_v, to
+ * the force on v (minus the gradient of K (|dq| - L)^2 / 2); |dq| = 0 adds 0. */
+
+int orc_spring_rest(int64_t ne, const int32_t *tail, const int32_t *head, const double *X, double *rest) {
+    for (int64_t e = 0; e < ne; ++e) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            const double t = X[3 * (int64_t)head[e] + k] - X[3 * (int64_t)tail[e] + k];
+            s += t * t;
+        }
+        rest[e] = sqrt(s);
+    }
+    return ORC_OK;
+}
+
+int orc_spring_forces(int64_t nv, int64_t ne, const int32_t *tail, const int32_t *head, const double *rest,
+                      double K, const double *q, double *force) {
+    for (int64_t e = 0; e < ne; ++e) {
+        const int64_t v = tail[e], h = head[e];
+        if (v < 0 || v >= nv || h < 0 || h >= nv) return ORC_E_ARG;
+        double dq[3], n2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            dq[k] = q[3 * h + k] - q[3 * v + k];
+            n2 += dq[k] * dq[k];
+        }
+        const double n = sqrt(n2);
+        for (int k = 0; k < 3; ++k) {
+            const double dir = n > 0.0 ? dq[k] / n : 0.0;
+            force[3 * v + k] += K * (dq[k] - rest[e] * dir);
+        }
+    }
+    return ORC_OK;
+}
+
+int orc_spring_apply(int64_t nv, const double *mass, double dt, double *q, double *qd, double *force) {
+    for (int64_t v = 0; v < nv; ++v)
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = 3 * v + k;
+            const double a = force[i] / mass[v];
+            q[i] += qd[i] * dt + 0.5 * a * dt * dt;
+            qd[i] += a * dt;
+            force[i] = 0.0;
+        }
+    return ORC_OK;
+}
+
+double orc_kinetic_energy(int64_t nv, const double *mass, const double *qd) {
+    double E = 0.0;
+    for (int64_t v = 0; v < nv; ++v)
+        E += 0.5 * mass[v] * (qd[3 * v] * qd[3 * v] + qd[3 * v + 1] * qd[3 * v + 1] + qd[3 * v + 2] * qd[3 * v + 2]);
+    return E;
+}
+
 /* ---- grouping and reordering ------------------------------------------------ */
 
 typedef struct { int64_t key; int64_t val; } kv_t;

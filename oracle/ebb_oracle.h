@@ -105,6 +105,16 @@ int orc_assemble(int model, int64_t nv, int64_t nt, const int32_t *tets,
 int orc_spmv(int64_t nv, const int64_t *row_ptr, const int32_t *col, const double *blocks,
              const double *u, double *y);
 
+/* Spring-mass workload: rest[e] = |X_head - X_tail|; force[tail] += K (dq - rest dq/|dq|)
+ * over the edges in row order (dq = q_head - q_tail; 0 if |dq| = 0); the exclusive
+ * update a = force/mass, q += qd dt + a dt^2/2, qd += a dt, force = 0; the kinetic
+ * energy sum of mass |qd|^2 / 2.  Vectors (nv, 3). */
+int orc_spring_rest(int64_t ne, const int32_t *tail, const int32_t *head, const double *X, double *rest);
+int orc_spring_forces(int64_t nv, int64_t ne, const int32_t *tail, const int32_t *head, const double *rest,
+                      double K, const double *q, double *force);
+int orc_spring_apply(int64_t nv, const double *mass, double dt, double *q, double *qd, double *force);
+double orc_kinetic_energy(int64_t nv, const double *mass, const double *qd);
+
 /* Grouping of the tets.v[4] key-field by vertex: CSR of incidence 4t+c,
  * rows in (t, c) order.  row_ptr: nv+1, inc: 4 nt. */
 int orc_group_by(int64_t nv, int64_t nt, const int32_t *tets, int64_t *row_ptr, int32_t *inc);

@@ -254,6 +254,45 @@ def adjoint_recipe(mesh: Mesh, seed: int = 2, n_fd: int = 32):
     return E, target, fd_tets
 
 
+def directed_edges(tets: np.ndarray, nv: int):
+    """The edges relation of a tet mesh as the spring-mass example uses it: every
+    ordered pair (tail, head) of distinct corners of some tet, without repeats,
+    sorted by tail, then head.  Returns (tail, head) int32 arrays."""
+    t = np.asarray(tets, dtype=np.int64)
+    a = np.repeat(t, 4, axis=1).ravel()
+    b = np.tile(t, (1, 4)).ravel()
+    keep = a != b
+    key = np.unique(a[keep] * nv + b[keep])
+    return (key // nv).astype(np.int32), (key % nv).astype(np.int32)
+
+
+@dataclass
+class SpringWorkload:
+    name: str
+    mesh: Mesh
+    tail: np.ndarray
+    head: np.ndarray
+    mass: np.ndarray      # (nv,) per-vertex mass
+    q0: np.ndarray        # (nv, 3) initial positions
+    qd0: np.ndarray       # (nv, 3) initial velocities
+    K: float
+    dt: float
+
+
+def workload_springs(n: int = 64, seed: int = 5) -> SpringWorkload:
+    """Spring-mass example on the n^3 Kuhn cube: springs on its directed edges
+    (rest lengths from the rest positions), masses (1 +- 0.5 uniform) / nv,
+    positions perturbed by up to 0.1 h and velocities up to 0.05 per axis
+    (uniform), K = 1, dt = 1e-4, in that draw order."""
+    m = kuhn_cube(n)
+    tail, head = directed_edges(m.tets, m.nv)
+    rng = np.random.default_rng(seed)
+    mass = (1.0 + 0.5 * rng.uniform(-1.0, 1.0, m.nv)) / m.nv
+    q0 = m.X + (0.1 / n) * rng.uniform(-1.0, 1.0, (m.nv, 3))
+    qd0 = 0.05 * rng.uniform(-1.0, 1.0, (m.nv, 3))
+    return SpringWorkload(f"springs_cube{n}", m, tail, head, mass, q0, qd0, 1.0, 1e-4)
+
+
 def soa(a: np.ndarray) -> np.ndarray:
     """(n, k) row-major -> (k, n) contiguous: the column-store layout."""
     return np.ascontiguousarray(np.asarray(a).T)

@@ -532,6 +532,92 @@ def test_assembled_rest_blocks_are_linear_elasticity(model):
 
 
 # --------------------------------------------------------------------------
+# spring-mass workload (the paper's introductory example)
+# --------------------------------------------------------------------------
+
+def _two_masses(K=3.0, m=(2.0, 0.5)):
+    X = np.array([[0.0, 0.0, 0.0], [1.0, 0.0, 0.0]])
+    return oracle.Springs(X, [0, 1], [1, 0], np.array(m), K)
+
+
+def test_spring_two_masses_closed_form():
+    sp = _two_masses()
+    assert np.allclose(sp.rest[:2], [1.0, 1.0], rtol=0, atol=0)
+    q = np.array([[0.0, 0.0, 0.0], [1.5, 0.0, 0.0]])       # stretched by 0.5
+    f = sp.forces(q)
+    assert np.allclose(f, [[1.5, 0, 0], [-1.5, 0, 0]], rtol=0, atol=1e-15)   # K * 0.5, restoring
+    q = np.array([[0.0, 0.0, 0.0], [0.0, 0.8, 0.0]])       # compressed along y
+    f = sp.forces(q)
+    assert np.allclose(f, [[0, -0.6, 0], [0, 0.6, 0]], rtol=0, atol=1e-15)
+    qd = np.array([[0.1, 0.0, 0.0], [0.0, 0.0, -0.2]])
+    dt = 0.01
+    q1, qd1 = sp.step(q, qd, dt)
+    a = f / sp.mass[:, None]
+    assert np.allclose(q1, q + qd * dt + 0.5 * a * dt * dt, rtol=0, atol=1e-16)
+    assert np.allclose(qd1, qd + a * dt, rtol=0, atol=1e-16)
+
+
+def test_spring_harmonic_oscillation():
+    # two masses on one spring: the separation oscillates about the rest length with
+    # omega^2 = K (1/m0 + 1/m1); the explicit update follows it to O(dt) over a period
+    K, m = 3.0, (2.0, 0.5)
+    sp = _two_masses(K, m)
+    w = np.sqrt(K * (1 / m[0] + 1 / m[1]))
+    A, dt = 0.01, 1e-4
+    q = np.array([[0.0, 0.0, 0.0], [1.0 + A, 0.0, 0.0]])
+    qd = np.zeros((2, 3))
+    steps = int(round(2 * np.pi / w / dt))
+    sep = []
+    for _ in range(steps):
+        q, qd = sp.step(q, qd, dt)
+        sep.append(q[1, 0] - q[0, 0] - 1.0)
+    t = dt * np.arange(1, steps + 1)
+    assert np.max(np.abs(np.array(sep) - A * np.cos(w * t))) <= 0.02 * A
+    # momentum is conserved exactly up to rounding (equal and opposite forces)
+    p = (sp.mass[:, None] * qd).sum(axis=0)
+    assert np.max(np.abs(p)) <= 1e-15
+
+
+def test_spring_forces_sum_zero_gradient_and_rest():
+    m, _, _ = mg.scramble(mg.jitter(mg.kuhn_cube(3), 0.05, seed=4), seed=6)
+    tail, head = mg.directed_edges(m.tets, m.nv)
+    # the edge set is symmetric and free of self-pairs
+    pairs = set(zip(tail.tolist(), head.tolist()))
+    assert all((b, a) in pairs and a != b for a, b in pairs)
+    sp = oracle.Springs(m.X, tail, head, np.ones(m.nv), 2.5)
+    f0 = sp.forces(m.X)
+    assert np.abs(f0).max() <= 1e-14
+    rng = _rng(41)
+    q = m.X + 0.05 * rng.standard_normal((m.nv, 3))
+    f = sp.forces(q)
+    assert np.abs(f.sum(axis=0)).max() <= 1e-13 * np.abs(f).max()
+
+    def V(qq):   # each undirected spring twice, so a quarter K per directed edge
+        dq = qq[head] - qq[tail]
+        return 0.25 * 2.5 * np.sum((np.linalg.norm(dq, axis=1) - sp.rest[: len(tail)]) ** 2)
+
+    eps = 1e-6
+    for _ in range(3):
+        a = rng.standard_normal((m.nv, 3))
+        fd = (V(q + eps * a) - V(q - eps * a)) / (2 * eps)
+        assert np.sum(f * a) == pytest.approx(-fd, rel=1e-7)
+
+
+def test_spring_free_flight_and_energy():
+    m = mg.jitter(mg.kuhn_cube(2), 0.02, seed=2)
+    tail, head = mg.directed_edges(m.tets, m.nv)
+    rng = _rng(42)
+    mass = rng.uniform(0.5, 1.5, m.nv)
+    sp = oracle.Springs(m.X, tail, head, mass, 0.0)      # K = 0: free flight
+    q = m.X + 0.1 * rng.standard_normal((m.nv, 3))
+    qd = rng.standard_normal((m.nv, 3))
+    q1, qd1 = sp.step(q, qd, 0.01)
+    assert np.array_equal(qd1, qd)
+    assert np.max(np.abs(q1 - (q + 0.01 * qd))) <= 1e-16
+    assert sp.kinetic_energy(qd) == pytest.approx(0.5 * np.sum(mass[:, None] * qd * qd), rel=1e-14)
+
+
+# --------------------------------------------------------------------------
 # Rayleigh damping (Vega's step computes damping with forces and stiffness:
 # Performance Evaluation); D = alpha M - beta K with K = df/dx
 # --------------------------------------------------------------------------
