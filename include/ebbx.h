@@ -79,6 +79,7 @@ typedef enum { EBBX_F32 = 0, EBBX_F64 = 1, EBBX_I32 = 2, EBBX_U8 = 3, EBBX_I64 =
 typedef struct ebbx_relation_s *ebbx_relation;
 typedef struct ebbx_fem_s *ebbx_fem;
 typedef struct ebbx_batch_s *ebbx_batch;
+typedef struct ebbx_springs_s *ebbx_springs;
 typedef void *ebbx_stream;   /* hipStream_t */
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -344,6 +345,50 @@ ebbx_status ebbx_fem_edge_count(ebbx_fem fem, int64_t *n_edges);
  * col (n_edges int32), blocks (9, n_edges) FP64, column q = 3 r + c of every
  * block (EBBX_E_STATE for blocks before any assembly).  Enqueued on stream. */
 ebbx_status ebbx_fem_edges_get(ebbx_fem fem, int32_t *row_ptr, int32_t *col, double *blocks, ebbx_stream stream);
+
+/* ---- the spring-mass workload -------------------------------------------- */
+
+/* The paper's introductory example (Ebb by example: a spring-mass simulation
+ * on a tet mesh) on the same relational runtime: a spring on every row of
+ * `edges`, whose arity-1 key-fields `tail` and `head` refer to rows of verts.
+ * Creation groups the edges by tail (ebbx_relation_group_by), computes every
+ * rest length |X_head - X_tail| from the FP64 (3, nv) field pos_field of verts
+ * (the example's per-edge kernel) and keeps row-ordered copies of the heads
+ * and rest lengths: later changes to the relations do not affect the domain.
+ * Synchronous.  K: the spring constant (finite). */
+ebbx_status ebbx_springs_create(ebbx_relation edges, const char *tail, const char *head, ebbx_relation verts,
+                                const char *pos_field, double K, ebbx_springs *out);
+ebbx_status ebbx_springs_destroy(ebbx_springs sp);
+
+/* Rest lengths (FP64, one per edge) in the order of the edges grouped by tail
+ * (each vertex's edges in increasing row order). */
+ebbx_status ebbx_springs_rest(ebbx_springs sp, double *rest_dev, ebbx_stream stream);
+
+/* force (+)= for every vertex v, the sum over the edges leaving v of
+ * K (dq - L dq / |dq|), dq = q_head - q_v (0 if |dq| = 0): restoring springs,
+ * minus the gradient of K (|dq| - L)^2 / 2 (the example's query loop over
+ * v.edges reducing into v.force; the printed listing has the opposite sign).
+ * FP64 (3, nv) vectors; each vertex's sum in a fixed order.  EBBX_E_PHASE if
+ * force aliases q. */
+ebbx_status ebbx_springs_forces(ebbx_springs sp, const double *q, double *force, int32_t accumulate,
+                                ebbx_stream stream);
+
+/* The example's exclusive per-vertex update: a = force / mass,
+ * q += qd dt + a dt^2 / 2, qd += a dt, force = 0.  mass: FP64 (nv).
+ * EBBX_E_PHASE if q, qd and force alias. */
+ebbx_status ebbx_springs_apply(ebbx_springs sp, const double *mass, double dt, double *q, double *qd,
+                               double *force, ebbx_stream stream);
+
+/* E_dev[0] += sum over vertices of mass |qd|^2 / 2 (a global +=; fixed-order
+ * two-pass sum, bitwise reproducible). */
+ebbx_status ebbx_springs_kinetic_energy(ebbx_springs sp, const double *mass, const double *qd, double *E_dev,
+                                        ebbx_stream stream);
+
+/* nsteps of (ebbx_springs_forces with accumulate = 1; ebbx_springs_apply),
+ * replayed from a HIP graph of 32 captured steps (recaptured when the
+ * pointers or dt change).  force must be zero on entry (apply leaves it zero). */
+ebbx_status ebbx_springs_run(ebbx_springs sp, const double *mass, double dt, int32_t nsteps, double *q,
+                             double *qd, double *force, ebbx_stream stream);
 
 /* ---- adjoint (vector-Jacobian products) ---------------------------------- */
 

@@ -126,6 +126,13 @@ def lib():
         "ebbx_fem_spmv": ([P, P, P, I32_, P], I32_),
         "ebbx_fem_edge_count": ([P, C.POINTER(I64_)], I32_),
         "ebbx_fem_edges_get": ([P, P, P, P, P], I32_),
+        "ebbx_springs_create": ([P, S, S, P, S, D, C.POINTER(P)], I32_),
+        "ebbx_springs_destroy": ([P], I32_),
+        "ebbx_springs_rest": ([P, P, P], I32_),
+        "ebbx_springs_forces": ([P, P, P, I32_, P], I32_),
+        "ebbx_springs_apply": ([P, P, D, P, P, P, P], I32_),
+        "ebbx_springs_kinetic_energy": ([P, P, P, P, P], I32_),
+        "ebbx_springs_run": ([P, P, D, I32_, P, P, P, P], I32_),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -613,3 +620,85 @@ class FemMesh:
             out[self.tperm.cpu().numpy()] = a
             a = out
         return a
+
+
+class Springs:
+    """Spring-mass domain over an edges relation (key-fields tail, head -> verts); see ebbx_springs_create."""
+
+    def __init__(self, edges: Relation, verts: Relation, K: float, tail="tail", head="head", pos="X"):
+        h = C.c_void_p()
+        _check(lib().ebbx_springs_create(edges.h, tail.encode(), head.encode(), verts.h, pos.encode(), float(K),
+                                         C.byref(h)))
+        self.h = h
+        self.edges, self.verts = edges, verts
+        self.nv, self.ne = verts.size, edges.size
+
+    def _vec(self, t, what):
+        _dev(t, torch.float64, what)
+        if tuple(t.shape) != (3, self.nv):
+            raise ValueError(f"{what}: expected shape (3, {self.nv}), got {tuple(t.shape)}")
+
+    def rest(self, stream=None):
+        out = torch.empty(max(self.ne, 1), dtype=torch.float64, device="cuda")
+        _check(lib().ebbx_springs_rest(self.h, _ptr(out), _stream(stream)))
+        return out[: self.ne]
+
+    def forces(self, q, force=None, accumulate=False, stream=None):
+        self._vec(q, "q")
+        if force is None:
+            force = torch.zeros_like(q)
+        self._vec(force, "force")
+        _check(lib().ebbx_springs_forces(self.h, _ptr(q), _ptr(force), int(bool(accumulate)), _stream(stream)))
+        return force
+
+    def apply(self, mass, dt, q, qd, force, stream=None):
+        for t, n in ((q, "q"), (qd, "qd"), (force, "force")):
+            self._vec(t, n)
+        _dev(mass, torch.float64, "mass")
+        _check(lib().ebbx_springs_apply(self.h, _ptr(mass), float(dt), _ptr(q), _ptr(qd), _ptr(force),
+                                        _stream(stream)))
+
+    def kinetic_energy(self, mass, qd, E=None, stream=None):
+        self._vec(qd, "qd")
+        _dev(mass, torch.float64, "mass")
+        if E is None:
+            E = torch.zeros(1, dtype=torch.float64, device="cuda")
+        _check(lib().ebbx_springs_kinetic_energy(self.h, _ptr(mass), _ptr(qd), _ptr(E), _stream(stream)))
+        return E
+
+    def run(self, mass, dt, nsteps, q, qd, force, stream=None):
+        for t, n in ((q, "q"), (qd, "qd"), (force, "force")):
+            self._vec(t, n)
+        _dev(mass, torch.float64, "mass")
+        _check(lib().ebbx_springs_run(self.h, _ptr(mass), float(dt), int(nsteps), _ptr(q), _ptr(qd), _ptr(force),
+                                      _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _check(lib().ebbx_springs_destroy(self.h))
+            self.h = None
+
+
+class SpringMesh:
+    """Convenience: verts (rest positions X) and edges (tail, head key-fields) relations, then Springs.
+
+    X: (nv, 3) float64; tail, head: (ne,) int32 (numpy or torch)."""
+
+    def __init__(self, X, tail, head, K):
+        Xd = torch.as_tensor(X, dtype=torch.float64).t().contiguous().cuda()
+        nv = Xd.shape[1]
+        self.verts = Relation("verts", nv)
+        self.edges = Relation("edges", len(tail))
+        self.verts.bind_field("X", Xd)
+        self.edges.bind_keyfield("tail", self.verts, torch.as_tensor(tail).to(torch.int32).contiguous().cuda())
+        self.edges.bind_keyfield("head", self.verts, torch.as_tensor(head).to(torch.int32).contiguous().cuda())
+        self.springs = Springs(self.edges, self.verts, K)
+        self.nv = nv
+
+    @staticmethod
+    def to_dev(a):
+        return torch.as_tensor(a, dtype=torch.float64).t().contiguous().cuda()
+
+    @staticmethod
+    def from_dev(t):
+        return t.t().cpu().numpy()
