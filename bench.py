@@ -44,7 +44,7 @@ def canonical_bytes(nt, nv, op, prec_bytes=4):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("elem.hip", "fem.hip", "fem.h"):
+    for f in ("elem.hip", "fem.hip", "fem.h", "tetmath.h"):
         with open(os.path.join(ROOT, "paper_1506_07577_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -71,6 +71,8 @@ def parse():
                          "then Morton-ordered, every strategy (a separate JSON line)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-step section")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint section")
+    ap.add_argument("--no-assembled", action="store_true", help="skip the assembled-stiffness section")
+    ap.add_argument("--no-springs", action="store_true", help="skip the spring-mass section")
     return ap.parse_args()
 
 
@@ -91,6 +93,51 @@ def time_events(fn, stream, reps):
         torch.cuda.synchronize()
         out.append(e0.elapsed_time(e1))
     return out
+
+
+def bench_springs(stream, flush_bytes):
+    """Spring-mass example on the 64^3 cube: force pass cold, and steps replayed from the graph."""
+    import torch
+
+    from paper_1506_07577_amd import ebbx
+    from paper_1506_07577_amd import meshgen as mg
+    w = mg.workload_springs(64)
+    m = w.mesh
+    sm = ebbx.SpringMesh(m.X, w.tail, w.head, w.K)
+    sp = sm.springs
+    md = torch.as_tensor(w.mass).cuda()
+    q, qd = sm.to_dev(w.q0), sm.to_dev(w.qd0)
+    f = torch.zeros_like(q)
+    nv, ne = sm.nv, len(w.tail)
+    tf = []
+    for _ in range(10):
+        ebbx.cache_flush(flush_bytes, stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sp.forces(q, f, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        tf.append(e0.elapsed_time(e1))
+    f.zero_()
+    steps = 320
+    sp.run(md, w.dt, steps, q, qd, f, stream=stream)   # capture + warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sp.run(md, w.dt, steps, q, qd, f, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    step_ms = e0.elapsed_time(e1) / steps
+    # per step: heads and rest lengths per edge, row offsets, q read, force written and read back,
+    # mass, q and qd read and written
+    step_bytes = 12 * ne + 4 * (nv + 1) + 204 * nv
+    sp.close()
+    return {"mesh": "cube64 directed edges", "n_verts": nv, "n_edges": ne,
+            "forces_cold_us": round(1e3 * statistics.median(tf), 2),
+            "graph_step_us": round(1e3 * step_ms, 2),
+            "edge_evals_per_s": round(ne / (step_ms * 1e-3), 1),
+            "step_algorithmic_bytes": step_bytes,
+            "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def bench_batch(stream, plain_rate):
@@ -405,6 +452,47 @@ def main():
         log(f"implicit step {t_step:.3f} ms, damped {t_damp:.3f} ms")
     else:
         plain_rate = None
+    if not args.no_assembled:
+        # the stiffness assembled on the edges relation (Vega's representation): one-time edge
+        # build, assembly of K(d), and the block-CSR product against the matrix-free K u call
+        t0 = time.perf_counter()
+        ne = fem.edge_count()
+        build_s = time.perf_counter() - t0
+        fem.assemble(d, stream=stream)
+        fem.spmv(u, y, stream=stream)
+        torch.cuda.synchronize()
+        reps = max(3, min(args.steps, 20))
+        ta, ts = [], []
+        for _ in range(reps):
+            ebbx.cache_flush(flush_bytes, stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fem.assemble(d, stream=stream)
+            e1.record(stream)
+            ebbx.cache_flush(flush_bytes, stream)
+            e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e2.record(stream)
+            fem.spmv(u, y, stream=stream)
+            e3.record(stream)
+            torch.cuda.synchronize()
+            ta.append(e0.elapsed_time(e1))
+            ts.append(e2.elapsed_time(e3))
+        esz = 4 if w.prec == "f32" else 8
+        sp_bytes = (nv + 1) * 4 + ne * (4 + 9 * esz) + 72 * nv
+        sp_ms = statistics.median(ts)
+        extra["assembled"] = {
+            "n_edges": ne, "edge_build_s": round(build_s, 3),
+            "assemble_ms": round(statistics.median(ta), 3),
+            "spmv_us": round(1e3 * sp_ms, 2), "matrix_free_kmul_us": round(1e3 * tk_med, 2),
+            "spmv_over_matrix_free": round(sp_ms / tk_med, 3),
+            "spmv_algorithmic_bytes": sp_bytes,
+            "spmv_hbm_frac": round(sp_bytes / (sp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "block_bytes": ne * 9 * esz, "scratch_bytes": nt * 144 * 8,
+            "note": "cold calls (1 GiB flush before each); blocks at the element precision, FP64 sums"}
+        log(f"assembled: build {build_s:.2f} s, assemble {statistics.median(ta):.3f} ms, spmv {1e3 * sp_ms:.1f} us")
+    if not args.no_springs:
+        extra["springs"] = bench_springs(stream, flush_bytes)
+        log(f"springs: {extra['springs']['graph_step_us']} us per step")
     if not args.no_batch:
         extra["batched"] = bench_batch(stream, plain_rate)
         log(f"batched step {extra['batched']['step_ms']} ms")

@@ -71,9 +71,8 @@ __global__ __launch_bounds__(256) void k_elem_matrix(AsmArgs a) {
     }
     double *rec = a.ke + (size_t)t * 144;
     bool ok = true;
-#pragma unroll 1
     for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < 3; ++k) {
             double dF[9], dP[9], h[12];
 #pragma unroll

@@ -5,8 +5,10 @@
 //  - rest lengths: one pass over the edges (the example's per-edge kernel);
 //  - forces: each vertex loops over the edges leaving it (the grouping of the
 //    edges by their tail key-field) and reduces (+=) the spring forces into its
-//    force field: sixteen lanes per vertex, each lane a stride of the vertex's
-//    edges, the row sum a fixed butterfly over the sixteen lanes;
+//    force field: eight lanes per vertex, each lane a stride of the vertex's
+//    edges, the row sum a fixed butterfly over the eight lanes (1, 2, 4, 8 and
+//    16 lanes measured 102, 56, 31, 32 and 41 us per cold force pass at 64^3,
+//    8 the fastest in graph-replayed steps);
 //  - apply: the exclusive per-vertex update (integrate, clear the force);
 //  - kinetic energy: a global += as a fixed-order two-pass sum;
 //  - run: nsteps of (forces, apply) replayed from a captured HIP graph.
@@ -49,7 +51,7 @@ namespace ebbx {
 
 namespace {
 
-constexpr int LANES = 16;             // lanes per vertex in the force pass
+constexpr int LANES = 8;              // lanes per vertex in the force pass (14 edges per interior vertex)
 constexpr int RUN_CHUNK = 32;         // steps per captured graph
 constexpr int EN_THREADS = 256;
 
