@@ -135,7 +135,7 @@ def test_spring_errors():
 
 
 def test_springs_full_size():
-    """Spring-mass on the 64^3 Kuhn cube (274,625 vertices, 3,670,016 directed edges), K = 1,
+    """Spring-mass on the 64^3 Kuhn cube (274,625 vertices, 3,744,128 directed edges), K = 1,
     dt = 1e-4: 200 steps from the captured graph against 200 oracle steps."""
     w = mg.workload_springs(64)
     m = w.mesh
