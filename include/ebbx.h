@@ -201,7 +201,9 @@ typedef struct {
  * parameters mu = E/(2(1+nu)), lam = E nu/((1+nu)(1-2nu)), and the lumped mass
  * m_v = sum of rho V0/4 over incident tets.  EBBX_E_DEGENERATE if a tet has
  * V0 <= 0.  Groups tets by keyfield if not yet grouped.  The FEM keeps views
- * of the key-field and the pinned field.  Synchronous. */
+ * of the key-field and the pinned field; reorder the relations (e.g. Morton)
+ * before creating the domain, since a later ebbx_relation_reorder of tets or
+ * verts leaves the domain's per-tet data in the old order.  Synchronous. */
 ebbx_status ebbx_fem_create(ebbx_relation tets, const char *keyfield, ebbx_relation verts,
                             const char *pos_field, const char *pinned_field,
                             const ebbx_fem_params *params, ebbx_fem *out);
