@@ -357,7 +357,8 @@ ebbx_status ebbx_fem_edges_get(ebbx_fem fem, int32_t *row_ptr, int32_t *col, dou
  * rest length |X_head - X_tail| from the FP64 (3, nv) field pos_field of verts
  * (the example's per-edge kernel) and keeps row-ordered copies of the heads
  * and rest lengths: later changes to the relations do not affect the domain.
- * Synchronous.  K: the spring constant (finite). */
+ * Synchronous.  K: the spring constant (finite).  Calls on one domain share
+ * its scratch (energy partials, captured steps): order them on one stream. */
 ebbx_status ebbx_springs_create(ebbx_relation edges, const char *tail, const char *head, ebbx_relation verts,
                                 const char *pos_field, double K, ebbx_springs *out);
 ebbx_status ebbx_springs_destroy(ebbx_springs sp);
@@ -376,7 +377,7 @@ ebbx_status ebbx_springs_forces(ebbx_springs sp, const double *q, double *force,
                                 ebbx_stream stream);
 
 /* The example's exclusive per-vertex update: a = force / mass,
- * q += qd dt + a dt^2 / 2, qd += a dt, force = 0.  mass: FP64 (nv).
+ * q += qd dt + a dt^2 / 2, qd += a dt, force = 0.  mass: FP64 (nv), positive.
  * EBBX_E_PHASE if q, qd and force alias. */
 ebbx_status ebbx_springs_apply(ebbx_springs sp, const double *mass, double dt, double *q, double *qd,
                                double *force, ebbx_stream stream);
@@ -387,8 +388,9 @@ ebbx_status ebbx_springs_kinetic_energy(ebbx_springs sp, const double *mass, con
                                         ebbx_stream stream);
 
 /* nsteps of (ebbx_springs_forces with accumulate = 1; ebbx_springs_apply),
- * replayed from a HIP graph of 32 captured steps (recaptured when the
- * pointers or dt change).  force must be zero on entry (apply leaves it zero). */
+ * whole chunks of 32 replayed from a HIP graph captured on first use
+ * (recaptured when the pointers or dt change), the rest launched directly.
+ * force must be zero on entry (apply leaves it zero). */
 ebbx_status ebbx_springs_run(ebbx_springs sp, const double *mass, double dt, int32_t nsteps, double *q,
                              double *qd, double *force, ebbx_stream stream);
 

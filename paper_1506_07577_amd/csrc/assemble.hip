@@ -207,8 +207,6 @@ void build_edges(ebbx_fem_s *F, hipStream_t s) {
     up(F->e_col, col.data(), col.size() * sizeof(int32_t));
     up(F->e_gptr, gptr.data(), gptr.size() * sizeof(int32_t));
     up(F->e_gent, gent.data(), gent.size() * sizeof(uint32_t));
-    F->e_blocks.reset(std::max<size_t>((size_t)9 * col.size() * F->esize, 8), s);
-    F->e_ke.reset(std::max<size_t>((size_t)nt * 144 * sizeof(double), 8), s);
 }
 
 namespace {
@@ -266,6 +264,11 @@ template <class T> void launch_spmv(ebbx_fem_s *F, const double *u, double *y, i
 
 void assemble_stiffness(ebbx_fem_s *F, const double *d, hipStream_t s) {
     build_edges(F, s);
+    // the blocks and the per-tet scratch, on the first assembly
+    const size_t blk_bytes = std::max<size_t>((size_t)9 * F->n_edges * F->esize, 8);
+    const size_t ke_bytes = std::max<size_t>((size_t)F->nt * 144 * sizeof(double), 8);
+    if (F->e_blocks.bytes() != blk_bytes) F->e_blocks.reset(blk_bytes, s);
+    if (F->e_ke.bytes() != ke_bytes) F->e_ke.reset(ke_bytes, s);
     if (F->prec == EBBX_F32) launch_assemble<float>(F, d, s);
     else launch_assemble<double>(F, d, s);
     F->assembled = true;

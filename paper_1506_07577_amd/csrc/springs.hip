@@ -308,7 +308,7 @@ extern "C" ebbx_status ebbx_springs_run(ebbx_springs sp, const double *mass, dou
     if (nv == 0 || nsteps == 0) return EBBX_OK;
     hipStream_t s = (hipStream_t)stream;
     const void *key[4] = {mass, q, qd, force};
-    if (!S->exec || !std::equal(key, key + 4, S->key) || S->key_dt != dt) {
+    if (nsteps >= RUN_CHUNK && (!S->exec || !std::equal(key, key + 4, S->key) || S->key_dt != dt)) {
         S->drop_graph();
         HIPCHK(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
         for (int k = 0; k < RUN_CHUNK; ++k) {
