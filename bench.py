@@ -442,8 +442,15 @@ def main():
 
         t_step, s = time_step(0.0, 0.0)
         plain_rate = nt * s.iters / (t_step * 1e-3)
+        # per CG iteration: the K p element map (same bytes as a K u call) plus the vector
+        # kernels (q = A p: y, p, mass, pinned in, q out; update: x, p, r, q, diag in, x, r, z
+        # out; p = z + beta p: z, p in, p out)
+        cg_bytes = bk + nv * (24 * 4 + 9 + 24 * 8 + 24 * 3)
         extra["implicit_step"] = {"ms": round(t_step, 3), "cg_iters": s.iters,
                                   "us_per_cg_iter": round(1e3 * t_step / max(s.iters, 1), 2),
+                                  "cg_iter_algorithmic_bytes": cg_bytes,
+                                  "cg_iter_hbm_frac": round(cg_bytes / (t_step * 1e-3 / max(s.iters, 1)) / 1e9
+                                                            / HBM_PEAK_GBS, 4),
                                   "tet_cg_iters_per_s": round(plain_rate, 1),
                                   "rel_res": s.rel_res, "status": s.status}
         t_damp, sd = time_step(2.5, 4e-3)
@@ -519,6 +526,41 @@ def main():
                "kind": "oracle",
                "sample": f"{reps} force+Kmul passes over the full {nt}-tet mesh (FP64, serial C "
                          f"oracle, 1 thread) in {el:.1f} s"}
+        # the oracle beside the other rows, on small bounded samples of the same workloads
+        rows = {}
+        t0 = time.perf_counter()
+        _d1, _v1, _dv, so = ref.implicit_step(dh, np.zeros_like(dh), w.dt, tol=0.0, maxit=5)
+        el = time.perf_counter() - t0
+        rows["implicit_step"] = {"value": round(nt * so.iters / el, 1), "unit": "tet CG iterations/s",
+                                 "sample": f"one step, 5 CG iterations, full mesh, {el:.2f} s (includes the "
+                                           f"force, K v and diagonal passes)"}
+        if "implicit_step" in extra:
+            rows["implicit_step"]["gpu_over_oracle"] = round(
+                extra["implicit_step"]["tet_cg_iters_per_s"] / rows["implicit_step"]["value"], 1)
+        if "assembled" in extra:
+            rp, col = oracle.edges(m.nv, m.tets)
+            blocks = ref.assemble(dh, rp, col)
+            t0 = time.perf_counter()
+            for _ in range(5):
+                oracle.spmv(rp, col, blocks, uh)
+            el = time.perf_counter() - t0
+            rows["assembled_spmv"] = {"value": round(5 * nt / el, 1), "unit": "tet-equivalent products/s",
+                                      "sample": f"5 block-CSR products, full mesh, {el:.2f} s"}
+            rows["assembled_spmv"]["gpu_over_oracle"] = round(
+                (nt / (extra["assembled"]["spmv_us"] * 1e-6)) / rows["assembled_spmv"]["value"], 1)
+        if "springs" in extra:
+            sw = mg.workload_springs(64)
+            sref = oracle.Springs(sw.mesh.X, sw.tail, sw.head, sw.mass, sw.K)
+            q1, qd1 = sw.q0, sw.qd0
+            t0 = time.perf_counter()
+            for _ in range(5):
+                q1, qd1 = sref.step(q1, qd1, sw.dt)
+            el = time.perf_counter() - t0
+            rows["springs"] = {"value": round(5 * len(sw.tail) / el, 1), "unit": "spring evals/s",
+                               "sample": f"5 steps, full 64^3 edge set, {el:.2f} s"}
+            rows["springs"]["gpu_over_oracle"] = round(extra["springs"]["edge_evals_per_s"] /
+                                                       rows["springs"]["value"], 1)
+        cpu["rows"] = rows
 
     out = {
         "metric": "tet force+Kmul evals/s (1.6M tets); batched & adjoint vs plain, same GPU",
