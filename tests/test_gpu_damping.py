@@ -213,3 +213,31 @@ def test_damped_plain_workload_residual():
     r = np.linalg.norm(((b - Ad) * free).ravel()) / np.linalg.norm((b * free).ravel())
     assert r <= max(10 * s.rel_res, 1e-5)
     mesh.fem.close()
+
+
+def test_randomized_damped_steps():
+    """Seeded sweep: 8 jittered (half of them scrambled) cubes of side 1..5, random model,
+    precision, strategy, material, damping and step; two fixed-count steps against the oracle."""
+    rng = np.random.default_rng(77)
+    for case in range(8):
+        n = int(rng.integers(1, 6))
+        m = mg.jitter(mg.kuhn_cube(n), 0.01, seed=int(rng.integers(1 << 30)))
+        if rng.random() < 0.5:
+            m, _, _ = mg.scramble(m, seed=int(rng.integers(1 << 30)))
+        model = int(rng.integers(0, 2))
+        prec = "f64" if rng.random() < 0.5 else "f32"
+        strat = ["atomic", "seg", "block", "owner"][int(rng.integers(0, 4))]
+        E, nu = float(10 ** rng.uniform(4, 6)), float(rng.uniform(0.25, 0.45))
+        alpha, beta = float(rng.uniform(0, 10)), float(10 ** rng.uniform(-4, -2))
+        dt = float(10 ** rng.uniform(-4, -2.5))
+        mesh, ref = _pair(m, model, prec, strat, E=E, nu=nu)
+        d0 = mg.perturbed_state(m, 0.005, seed=int(rng.integers(1 << 30)))
+        v0 = 0.05 * mg.direction(m, int(rng.integers(1 << 30)))
+        d, v = mesh.to_dev(d0), mesh.to_dev(v0)
+        for _ in range(2):
+            mesh.fem.implicit_step(d, v, dt, tol=0.0, maxit=30, alpha=alpha, beta=beta)
+            d0, v0, _dv, _ = ref.implicit_step(d0, v0, dt, tol=0.0, maxit=30, alpha=alpha, beta=beta)
+        bound = 1e-9 if prec == "f64" else 1e-5
+        case_id = (case, n, model, prec, strat, alpha, beta, dt)
+        assert nerr(mesh.from_dev(v), v0) <= bound, case_id
+        mesh.fem.close()

@@ -153,3 +153,29 @@ def test_springs_full_size():
     E = float(sm.springs.kinetic_energy(md, qd))
     assert abs(E - ref.kinetic_energy(qds)) <= 1e-9 * E
     sm.springs.close()
+
+
+def test_randomized_springs():
+    """Seeded sweep: 8 cubes of side 1..6 with shuffled (or sorted) edge rows, random K and dt:
+    forces, then 20 steps (launched directly) or 40 (one captured chunk of 32 plus 8) against the
+    oracle."""
+    rng = np.random.default_rng(123)
+    for case in range(8):
+        n = int(rng.integers(1, 7))
+        K = float(10 ** rng.uniform(-1, 1))
+        m, tail, head, mass, q0, qd0, sm, ref = _case(n=n, seed=int(rng.integers(1 << 20)), K=K,
+                                                    shuffle=bool(rng.random() < 0.5))
+        dt = float(10 ** rng.uniform(-5, -4))
+        md = torch.as_tensor(mass).cuda()
+        f = sm.springs.forces(sm.to_dev(q0))
+        case_id = (case, n, K, dt)
+        assert nerr(sm.from_dev(f), ref.forces(q0)) <= 1e-12, case_id
+        steps = 20 if case % 2 else 40
+        q, qd = sm.to_dev(q0), sm.to_dev(qd0)
+        f = torch.zeros_like(q)
+        sm.springs.run(md, dt, steps, q, qd, f)
+        qs, qds = q0, qd0
+        for _ in range(steps):
+            qs, qds = ref.step(qs, qds, dt)
+        assert nerr(sm.from_dev(qd), qds) <= 1e-10, case_id
+        sm.springs.close()
