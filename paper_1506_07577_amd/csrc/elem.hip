@@ -15,7 +15,9 @@
 //  - SEG:    one thread per tet writes its per-corner partials, then one thread
 //    per vertex sums them over the grouping's incidence in a fixed order;
 //  - BLOCK:  a workgroup takes a block of consecutive (Morton-ordered) tets,
-//    stages the block's vertices in LDS, evaluates, writes each corner's result
+//    stages the block's vertices in LDS (the fields and the rest positions, from
+//    which each tet recomputes B = Dm^-1 instead of streaming the stored B),
+//    evaluates, writes each corner's result
 //    to its row of the block's incidence order, sums each vertex's rows in a
 //    fixed order, stores the vertices it owns outright and writes partials of
 //    vertices shared with other blocks to a halo buffer that a vertex pass sums
@@ -150,6 +152,34 @@ __device__ __forceinline__ void reduce_slot(const ElemArgs &a, const T *s_h, uin
     }
 }
 
+// B = Dm^-1 and V0 = det(Dm)/6 of one tet from its corners' rest positions staged in
+// LDS (three columns of stride S): Dm from FP64 differences rounded to T, then the
+// adjugate over the determinant.  Recomputing B costs ~60 VALU per tet and saves the
+// 9 per-tet B values (36 B in FP32) of the stream.
+template <class T>
+__device__ __forceinline__ void rest_B(const double *s_x, uint32_t S, const uint32_t *sl, T *b, T &V0) {
+    double x0[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x0[k] = s_x[k * S + sl[0]];
+    T Dm[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Dm[3 * k + c] = (T)(s_x[k * S + sl[c + 1]] - x0[k]);
+    const T det = det3(Dm);
+    const T idet = t_rcp(det);
+    b[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) * idet;
+    b[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) * idet;
+    b[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) * idet;
+    b[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) * idet;
+    b[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) * idet;
+    b[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) * idet;
+    b[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) * idet;
+    b[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) * idet;
+    b[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) * idet;
+    V0 = det * T(1.0 / 6.0);
+}
+
 template <class T, int MODEL, int OP, int TPT, int W, int RED>
 __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     extern __shared__ uint4 s_dyn4[];
@@ -176,7 +206,8 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     double *s_d = (double *)s_dyn4;
     double *s_u = s_d + 3 * S;
     double *s_w = s_u + 3 * S;
-    T *s_h = (T *)(s_d + 3 * NQ * S);
+    double *s_x = s_d + 3 * NQ * S;   // rest positions of the block's vertices
+    T *s_h = (T *)(s_x + 3 * S);
     double *s_acc = (double *)s_h;
 
     // this thread's first block vertex
@@ -198,9 +229,6 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     for (int r = 0; r < TPT; ++r) {
         const uint32_t t = t0 + r * nthr + tid;
         if (t < nt) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k) b[r][k] = ldc<T>(a.B[k], t);
-            V0[r] = tet_V0(b[r]);
             if (a.mu_t) {
                 mu[r] = ldc<T>(a.mu_t, t);
                 lam[r] = ldc<T>(a.lam_t, t);
@@ -219,6 +247,7 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * S + tid] = ldc<double>(a.d[k], gv0);
+            s_x[k * S + tid] = ldc<double>(a.X[k], gv0);
             if (NQ > 1) s_u[k * S + tid] = ldc<double>(a.u[k], gv0);
             if (NQ > 2) s_w[k * S + tid] = ldc<double>(a.w[k], gv0);
             if (RED == 1) s_acc[k * S + tid] = 0.0;
@@ -231,6 +260,7 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * S + i] = ldc<double>(a.d[k], gv);
+            s_x[k * S + i] = ldc<double>(a.X[k], gv);
             if (NQ > 1) s_u[k * S + i] = ldc<double>(a.u[k], gv);
             if (NQ > 2) s_w[k * S + i] = ldc<double>(a.w[k], gv);
             if (RED == 1) s_acc[k * S + i] = 0.0;
@@ -250,6 +280,7 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
                     qu[c][k] = (NQ > 1) ? s_u[k * S + sl[r][c]] : 0.0;
                     qw[c][k] = (NQ > 2) ? s_w[k * S + sl[r][c]] : 0.0;
                 }
+            rest_B(s_x, S, sl[r], b[r], V0[r]);
             T h[12];
             const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
             if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
@@ -588,6 +619,7 @@ static ElemArgs base_args(ebbx_fem_s *F) {
     }
     a.mu = F->mu;
     a.lam = F->lam;
+    for (int k = 0; k < 3; ++k) a.X[k] = F->Xc.as<double>() + (size_t)k * nv;
     a.n_inv = F->status.as<unsigned long long>();
     a.tmesh = F->tmesh;
     a.blk_verts = F->blk_verts.as<int32_t>();
@@ -616,7 +648,7 @@ static void set_vec(const double *(&dst)[3], const double *p, uint32_t nv) {
 
 size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
     const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
-    const size_t stage = (size_t)3 * nq * F->blk_maxv * sizeof(double);
+    const size_t stage = (size_t)3 * (nq + 1) * F->blk_maxv * sizeof(double);
     if (F->blk_red == 1) return stage + (size_t)3 * F->blk_maxv * sizeof(double);
     return stage + (size_t)12 * F->blk_tets * F->esize;
 }

@@ -19,6 +19,7 @@ struct ElemArgs {
     const void *V0;             // (nt) element precision
     const void *mu_t, *lam_t;   // per-tet Lame parameters (element precision) or NULL
     double mu, lam;             // uniform material when mu_t == NULL
+    const double *X[3];         // rest positions (library copy), for B recomputed per block
     const double *d[3];         // displacement columns
     const double *u[3];         // direction columns (stiffness product; `a` of T[a, w])
     const double *w[3];         // second direction columns (`w` of T[a, w])
@@ -131,7 +132,7 @@ struct ebbx_fem_s {
     bool batch_owned = false;        // the union domain of a batch: destroyed with it
     size_t esize = 8;   // bytes of one element-precision value
 
-    ebbx::DevBuf B, V0, mat, mass, pinned, part, status, scratch;
+    ebbx::DevBuf B, V0, mat, mass, pinned, part, status, scratch, Xc;
     // block strategy tables
     int32_t blk_tets = 0;      // tets per block
     int64_t nblk = 0;

@@ -130,6 +130,9 @@ std::unique_ptr<ebbx_fem_s> fem_build(ebbx_relation_s *tr, const char *keyfield,
     if (pin) HIPCHK(hipMemcpyAsync(F->pinned.get(), pin, (size_t)F->nv, hipMemcpyDeviceToDevice, s));
     else HIPCHK(hipMemsetAsync(F->pinned.get(), 0, (size_t)nv, s));
     const int64_t nbad = elem_precompute(F.get(), (const double *)X.ptr, E_tet, s);
+    F->Xc.reset((size_t)std::max<int64_t>(3 * vr->size, 1) * sizeof(double), s);
+    if (vr->size > 0)
+        HIPCHK(hipMemcpy(F->Xc.get(), X.ptr, (size_t)(3 * vr->size) * sizeof(double), hipMemcpyDeviceToDevice));
     if (nbad > 0) fail(EBBX_E_DEGENERATE, "%lld rest tets have V0 <= 0", (long long)nbad);
     set_strategy(F.get(), params->strategy, params->block, s);
     HIPCHK(hipStreamSynchronize(s));
