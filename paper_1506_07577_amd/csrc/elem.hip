@@ -15,8 +15,9 @@
 //  - SEG:    one thread per tet writes its per-corner partials, then one thread
 //    per vertex sums them over the grouping's incidence in a fixed order;
 //  - BLOCK:  a workgroup takes a block of consecutive (Morton-ordered) tets,
-//    stages the block's vertices in LDS (the fields and the rest positions, from
-//    which each tet recomputes B = Dm^-1 instead of streaming the stored B),
+//    stages the block's vertices in LDS (the fields and, for blocks of at most 256
+//    vertices, the rest positions, from which each tet recomputes B = Dm^-1
+//    instead of streaming the stored B),
 //    evaluates, writes each corner's result
 //    to its row of the block's incidence order, sums each vertex's rows in a
 //    fixed order, stores the vertices it owns outright and writes partials of
@@ -206,8 +207,12 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     double *s_d = (double *)s_dyn4;
     double *s_u = s_d + 3 * S;
     double *s_w = s_u + 3 * S;
-    double *s_x = s_d + 3 * NQ * S;   // rest positions of the block's vertices
-    T *s_h = (T *)(s_x + 3 * S);
+    // blocks of at most 256 vertices (8-bit corner slots, a well-ordered mesh) stage the rest
+    // positions and recompute B per tet; others stream the stored B (their vertex gathers are
+    // scattered, and the 24 B per block vertex would cost more than the 36-72 B per tet)
+    constexpr bool XB = W == 1;
+    double *s_x = s_d + 3 * NQ * S;   // rest positions of the block's vertices (XB)
+    T *s_h = (T *)(s_x + (XB ? 3 * S : 0));
     double *s_acc = (double *)s_h;
 
     // this thread's first block vertex
@@ -229,6 +234,11 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     for (int r = 0; r < TPT; ++r) {
         const uint32_t t = t0 + r * nthr + tid;
         if (t < nt) {
+            if (!XB) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) b[r][k] = ldc<T>(a.B[k], t);
+                V0[r] = tet_V0(b[r]);
+            }
             if (a.mu_t) {
                 mu[r] = ldc<T>(a.mu_t, t);
                 lam[r] = ldc<T>(a.lam_t, t);
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * S + tid] = ldc<double>(a.d[k], gv0);
-            s_x[k * S + tid] = ldc<double>(a.X[k], gv0);
+            if (XB) s_x[k * S + tid] = ldc<double>(a.X[k], gv0);
             if (NQ > 1) s_u[k * S + tid] = ldc<double>(a.u[k], gv0);
             if (NQ > 2) s_w[k * S + tid] = ldc<double>(a.w[k], gv0);
             if (RED == 1) s_acc[k * S + tid] = 0.0;
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * S + i] = ldc<double>(a.d[k], gv);
-            s_x[k * S + i] = ldc<double>(a.X[k], gv);
+            if (XB) s_x[k * S + i] = ldc<double>(a.X[k], gv);
             if (NQ > 1) s_u[k * S + i] = ldc<double>(a.u[k], gv);
             if (NQ > 2) s_w[k * S + i] = ldc<double>(a.w[k], gv);
             if (RED == 1) s_acc[k * S + i] = 0.0;
@@ -280,7 +290,7 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
                     qu[c][k] = (NQ > 1) ? s_u[k * S + sl[r][c]] : 0.0;
                     qw[c][k] = (NQ > 2) ? s_w[k * S + sl[r][c]] : 0.0;
                 }
-            rest_B(s_x, S, sl[r], b[r], V0[r]);
+            if (XB) rest_B(s_x, S, sl[r], b[r], V0[r]);
             T h[12];
             const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
             if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
@@ -648,7 +658,8 @@ static void set_vec(const double *(&dst)[3], const double *p, uint32_t nv) {
 
 size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
     const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
-    const size_t stage = (size_t)3 * (nq + 1) * F->blk_maxv * sizeof(double);
+    const int nx = F->blk_w == 1 ? 1 : 0;   // rest positions staged (blocks of <= 256 vertices)
+    const size_t stage = (size_t)3 * (nq + nx) * F->blk_maxv * sizeof(double);
     if (F->blk_red == 1) return stage + (size_t)3 * F->blk_maxv * sizeof(double);
     return stage + (size_t)12 * F->blk_tets * F->esize;
 }
