@@ -19,7 +19,8 @@
 //    vertices, the rest positions, from which each tet recomputes B = Dm^-1
 //    instead of streaming the stored B),
 //    evaluates, writes each corner's result
-//    to its row of the block's incidence order, sums each vertex's rows in a
+//    to its row of the block's incidence order (FP64 rows overwrite the staging
+//    after a barrier, so that they do not limit the workgroups per CU), sums each vertex's rows in a
 //    fixed order, stores the vertices it owns outright and writes partials of
 //    vertices shared with other blocks to a halo buffer that a vertex pass sums
 //    in block order.  No global atomics (BLOCK_LDS: the in-block sums with LDS
@@ -181,6 +182,18 @@ __device__ __forceinline__ void rest_B(const double *s_x, uint32_t S, const uint
     V0 = det * T(1.0 / 6.0);
 }
 
+// Gradient dD B of a vertex field staged in LDS (3 columns of S block vertices) over the
+// tet whose corners sit in slots sl.
+template <class T>
+__device__ __forceinline__ void staged_grad(const double *s, uint32_t S, const uint32_t *sl, const T *b, T *G) {
+    double q[4][3];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) q[c][k] = s[k * S + sl[c]];
+    grad_from(q, b, G);
+}
+
 template <class T, int MODEL, int OP, int TPT, int W, int RED>
 __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     extern __shared__ uint4 s_dyn4[];
@@ -212,7 +225,7 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
     // scattered, and the 24 B per block vertex would cost more than the 36-72 B per tet)
     constexpr bool XB = W == 1;
     double *s_x = s_d + 3 * NQ * S;   // rest positions of the block's vertices (XB)
-    T *s_h = (T *)(s_x + (XB ? 3 * S : 0));
+    T *s_h = (T *)(s_x + (XB ? 3 * S : 0));   // rows (moved to the LDS start when REUSE)
     double *s_acc = (double *)s_h;
 
     // this thread's first block vertex
@@ -277,36 +290,89 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
         }
     }
     __syncthreads();
+    // FP64 per-corner rows (24 KiB per 256 tets) would cap the workgroups per CU when added to
+    // the staging: there every tet first takes its gradients from the staged fields into
+    // registers, and after a barrier the rows overwrite the staging from the start of the LDS.
+    // FP32 rows are half as large and keep the single pass.
+    constexpr bool REUSE = sizeof(T) == 8 && RED == 0;
+    if (REUSE) {
+        T G[TPT][9], D1[TPT][9], D2[TPT][9];
 #pragma unroll
-    for (int r = 0; r < TPT; ++r) {
-        const uint32_t tl = r * nthr + tid, t = t0 + tl;
-        if (t < nt) {
-            double qd[4][3], qu[4][3], qw[4][3];
+        for (int r = 0; r < TPT; ++r) {
+            const uint32_t t = t0 + r * nthr + tid;
+            if (t < nt) {
+                if (XB) rest_B(s_x, S, sl[r], b[r], V0[r]);
+                staged_grad(s_d, S, sl[r], b[r], G[r]);
+                if (NQ > 1) staged_grad(s_u, S, sl[r], b[r], D1[r]);
+                if (NQ > 2) staged_grad(s_w, S, sl[r], b[r], D2[r]);
+            }
+        }
+        __syncthreads();
+        T *s_r = (T *)s_dyn4;
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int k = 0; k < 3; ++k) {
-                    qd[c][k] = s_d[k * S + sl[r][c]];
-                    qu[c][k] = (NQ > 1) ? s_u[k * S + sl[r][c]] : 0.0;
-                    qw[c][k] = (NQ > 2) ? s_w[k * S + sl[r][c]] : 0.0;
+        for (int r = 0; r < TPT; ++r) {
+            const uint32_t t = t0 + r * nthr + tid;
+            if (t < nt) {
+                T h[12];
+                bool ok = true;
+                if (OP == OP_TMUL) {
+                    T Q[9];
+                    ok = d2stress_scaled<T, MODEL>(mu[r], lam[r], V0[r], G[r], D1[r], D2[r], Q);
+                    corner_out(Q, b[r], h);
+                } else if (OP == OP_FORCE) {
+                    T P[9];
+                    ok = stress_scaled<T, MODEL>(mu[r], lam[r], V0[r], G[r], P);
+                    corner_out(P, b[r], h);
+                } else if (OP == OP_KMUL) {
+                    T dP[9];
+                    ok = dstress_scaled<T, MODEL>(mu[r], lam[r], V0[r], G[r], D1[r], dP);
+                    corner_out(dP, b[r], h);
+                } else {
+                    ok = diag12<T, MODEL>(mu[r], lam[r], G[r], b[r], V0[r], h);
                 }
-            if (XB) rest_B(s_x, S, sl[r], b[r], V0[r]);
-            T h[12];
-            const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
-            if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
-            if (RED == 0) {
+                if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
                 const uint32_t p[4] = {pw[r][0] & 0xffffu, pw[r][0] >> 16, pw[r][1] & 0xffffu, pw[r][1] >> 16};
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    s_h[p[c]] = h[3 * c];
-                    s_h[LB + p[c]] = h[3 * c + 1];
-                    s_h[2 * LB + p[c]] = h[3 * c + 2];
+                    s_r[p[c]] = h[3 * c];
+                    s_r[LB + p[c]] = h[3 * c + 1];
+                    s_r[2 * LB + p[c]] = h[3 * c + 2];
                 }
-            } else {
+            }
+        }
+        s_h = s_r;
+    } else {
+#pragma unroll
+        for (int r = 0; r < TPT; ++r) {
+            const uint32_t tl = r * nthr + tid, t = t0 + tl;
+            if (t < nt) {
+                double qd[4][3], qu[4][3], qw[4][3];
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) atomicAdd(&s_acc[k * S + sl[r][c]], (double)h[3 * c + k]);
+                    for (int k = 0; k < 3; ++k) {
+                        qd[c][k] = s_d[k * S + sl[r][c]];
+                        qu[c][k] = (NQ > 1) ? s_u[k * S + sl[r][c]] : 0.0;
+                        qw[c][k] = (NQ > 2) ? s_w[k * S + sl[r][c]] : 0.0;
+                    }
+                if (XB) rest_B(s_x, S, sl[r], b[r], V0[r]);
+                T h[12];
+                const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
+                if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
+                if (RED == 0) {
+                    const uint32_t p[4] = {pw[r][0] & 0xffffu, pw[r][0] >> 16, pw[r][1] & 0xffffu, pw[r][1] >> 16};
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        s_h[p[c]] = h[3 * c];
+                        s_h[LB + p[c]] = h[3 * c + 1];
+                        s_h[2 * LB + p[c]] = h[3 * c + 2];
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+#pragma unroll
+                        for (int k = 0; k < 3; ++k) atomicAdd(&s_acc[k * S + sl[r][c]], (double)h[3 * c + k]);
+                }
             }
         }
     }
@@ -661,6 +727,7 @@ size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
     const int nx = F->blk_w == 1 ? 1 : 0;   // rest positions staged (blocks of <= 256 vertices)
     const size_t stage = (size_t)3 * (nq + nx) * F->blk_maxv * sizeof(double);
     if (F->blk_red == 1) return stage + (size_t)3 * F->blk_maxv * sizeof(double);
+    if (F->esize == 8) return std::max(stage, (size_t)12 * F->blk_tets * F->esize);   // rows reuse the staging
     return stage + (size_t)12 * F->blk_tets * F->esize;
 }
 
