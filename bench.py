@@ -128,9 +128,9 @@ def bench_springs(stream, flush_bytes):
     e1.record(stream)
     torch.cuda.synchronize()
     step_ms = e0.elapsed_time(e1) / steps
-    # per step: heads and rest lengths per edge, row offsets, q read, force written and read back,
-    # mass, q and qd read and written
-    step_bytes = 12 * ne + 4 * (nv + 1) + 204 * nv
+    # per step, the least a step must move: heads and rest lengths per edge, row offsets, q read
+    # once (own and neighbour positions), the new q written, qd read and written, mass read
+    step_bytes = 12 * ne + 4 * (nv + 1) + 104 * nv
     sp.close()
     return {"mesh": "cube64 directed edges", "n_verts": nv, "n_edges": ne,
             "forces_cold_us": round(1e3 * statistics.median(tf), 2),

@@ -388,9 +388,15 @@ ebbx_status ebbx_springs_kinetic_energy(ebbx_springs sp, const double *mass, con
                                         ebbx_stream stream);
 
 /* nsteps of (ebbx_springs_forces with accumulate = 1; ebbx_springs_apply),
- * whole chunks of 32 replayed from a HIP graph captured on first use
- * (recaptured when the pointers or dt change), the rest launched directly.
- * force must be zero on entry (apply leaves it zero). */
+ * with the same results bit for bit.  Each step runs as one fused kernel
+ * (forces and update of every vertex) that writes the new positions to a
+ * second position buffer, 3 nv FP64 owned by sp (allocated on the first call,
+ * freed by ebbx_springs_destroy), and the next step writes them back; an odd
+ * nsteps starts with one step of the two separate passes, so the result is
+ * always in q.  Whole chunks of 32 steps are replayed from a HIP graph
+ * captured on first use (recaptured when the pointers or dt change), the rest
+ * launched directly.  The contents of force join the first step; force is
+ * zero on return. */
 ebbx_status ebbx_springs_run(ebbx_springs sp, const double *mass, double dt, int32_t nsteps, double *q,
                              double *qd, double *force, ebbx_stream stream);
 

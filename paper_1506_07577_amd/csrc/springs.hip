@@ -5,13 +5,14 @@
 //  - rest lengths: one pass over the edges (the example's per-edge kernel);
 //  - forces: each vertex loops over the edges leaving it (the grouping of the
 //    edges by their tail key-field) and reduces (+=) the spring forces into its
-//    force field: eight lanes per vertex, each lane a stride of the vertex's
-//    edges, the row sum a fixed butterfly over the eight lanes (1, 2, 4, 8 and
-//    16 lanes measured 102, 56, 31, 32 and 41 us per cold force pass at 64^3,
-//    8 the fastest in graph-replayed steps);
+//    force field: four lanes per vertex, each lane a stride of the vertex's
+//    edges with two edges' loads in flight, the row sum a fixed butterfly over
+//    the four lanes, one division per edge and K applied to the sum;
 //  - apply: the exclusive per-vertex update (integrate, clear the force);
 //  - kinetic energy: a global += as a fixed-order two-pass sum;
-//  - run: nsteps of (forces, apply) replayed from a captured HIP graph.
+//  - run: nsteps replayed from a captured HIP graph of 32 steps, each step one
+//    fused kernel (forces and update of a vertex together, positions ping-ponged
+//    through a second buffer so that no vertex reads an advanced neighbour).
 // Springs restore: edge (v -> h) adds K (dq - L dq/|dq|), dq = q_h - q_v.
 #include <algorithm>
 #include <cmath>
@@ -29,6 +30,7 @@ struct ebbx_springs_s {
     ebbx::DevBuf head;   // int32 (ne): head vertex of each edge, in row order
     ebbx::DevBuf rest;   // FP64 (ne): rest length of each edge, in row order
     ebbx::DevBuf part;   // FP64 partials of the energy sum
+    ebbx::DevBuf q2;     // FP64 (3 nv): the other position buffer of the fused steps of a run
     // captured steps of ebbx_springs_run
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
@@ -51,7 +53,8 @@ namespace ebbx {
 
 namespace {
 
-constexpr int LANES = 8;              // lanes per vertex in the force pass (14 edges per interior vertex)
+constexpr int LANES = 4;              // lanes per vertex in the force pass (14 edges per interior vertex)
+constexpr int UNROLL = 2;             // edges per lane with their loads in flight together
 constexpr int RUN_CHUNK = 32;         // steps per captured graph
 constexpr int EN_THREADS = 256;
 
@@ -82,45 +85,97 @@ __global__ void k_spring_setup(const int64_t *rp, const int32_t *inc, const int3
     }
 }
 
-__global__ __launch_bounds__(256) void k_spring_forces(const int32_t *row, const int32_t *head, const double *rest,
-                                                       double K, const double *q, double *f, uint32_t nv,
-                                                       int accumulate) {
-    const uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / LANES;
-    const uint32_t lane = threadIdx.x % LANES;
-    const uint32_t v = g < nv ? g : nv - 1;   // whole groups stay in the shuffles
-    const int32_t e0 = row[v], e1 = g < nv ? row[v + 1] : e0;
+// Sum over the edges leaving vertex v ([e0, e1) of the rows) of dq - L dq/|dq|, dq = q_h - q_v
+// (K is applied once to the sum): lane `lane` of the vertex's L lanes takes edges e0 + lane,
+// e0 + lane + L, ..., with the loads of U edges in flight at once; the lane sums are then
+// combined by a fixed butterfly, so every lane returns the same, order-fixed total.
+template <int L, int U>
+__device__ __forceinline__ void spring_sum(const int32_t *head, const double *rest, const double *q, uint32_t nv,
+                                           uint32_t v, int32_t e0, int32_t e1, uint32_t lane, double &f0, double &f1,
+                                           double &f2) {
     const double q0 = q[v], q1 = q[nv + v], q2 = q[2 * nv + v];
-    double f0 = 0.0, f1 = 0.0, f2 = 0.0;
-    for (int32_t e = e0 + (int32_t)lane; e < e1; e += LANES) {
-        const uint32_t h = (uint32_t)head[e];
-        const double a = q[h] - q0, b = q[nv + h] - q1, c = q[2 * nv + h] - q2;
-        const double n = sqrt(a * a + b * b + c * c);
-        const double L = rest[e];
-        if (n > 0.0) {
-            f0 += K * (a - L * (a / n));
-            f1 += K * (b - L * (b / n));
-            f2 += K * (c - L * (c / n));
-        } else {
-            f0 += K * a;
-            f1 += K * b;
-            f2 += K * c;
+    f0 = f1 = f2 = 0.0;
+    for (int32_t e = e0 + (int32_t)lane; e < e1; e += U * L) {
+        uint32_t h[U];
+        double len[U], a[U], b[U], c[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            ok[u] = e + u * L < e1;
+            h[u] = ok[u] ? (uint32_t)head[e + u * L] : v;
+            len[u] = ok[u] ? rest[e + u * L] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            a[u] = q[h[u]] - q0;
+            b[u] = q[nv + h[u]] - q1;
+            c[u] = q[2 * nv + h[u]] - q2;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const double n = sqrt(a[u] * a[u] + b[u] * b[u] + c[u] * c[u]);
+            const double sc = n > 0.0 ? len[u] / n : 0.0;   // a zero-length spring pulls with K dq
+            f0 += fma(-sc, a[u], a[u]);
+            f1 += fma(-sc, b[u], b[u]);
+            f2 += fma(-sc, c[u], c[u]);
         }
     }
 #pragma unroll
-    for (int m = LANES / 2; m >= 1; m >>= 1) {
-        f0 += __shfl_xor(f0, m, LANES);
-        f1 += __shfl_xor(f1, m, LANES);
-        f2 += __shfl_xor(f2, m, LANES);
+    for (int m = L / 2; m >= 1; m >>= 1) {
+        f0 += __shfl_xor(f0, m, L);
+        f1 += __shfl_xor(f1, m, L);
+        f2 += __shfl_xor(f2, m, L);
     }
-    if (lane == 0 && g < nv) {
-        if (accumulate) {
-            f0 += f[v];
-            f1 += f[nv + v];
-            f2 += f[2 * nv + v];
+}
+
+// The exclusive update of one vertex component: a = f / m, q += qd dt + a dt^2 / 2, qd += a dt.
+// Both the update pass and the fused step call it, so the two agree bit for bit.
+__device__ __forceinline__ void integrate(double q, double qd, double a, double dt, double &q_new, double &qd_new) {
+    q_new = q + (qd * dt + 0.5 * a * dt * dt);
+    qd_new = qd + a * dt;
+}
+
+// Force pass: lanes 0..2 of each vertex's group store (or += into) the x, y, z components.
+template <int L, int U>
+__global__ __launch_bounds__(256) void k_spring_forces(const int32_t *row, const int32_t *head, const double *rest,
+                                                       double K, const double *q, double *f, uint32_t nv,
+                                                       int accumulate) {
+    const uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const uint32_t lane = threadIdx.x % L;
+    const uint32_t v = g < nv ? g : nv - 1;   // whole groups stay in the shuffles
+    const int32_t e0 = row[v], e1 = g < nv ? row[v + 1] : e0;
+    double f0, f1, f2;
+    spring_sum<L, U>(head, rest, q, nv, v, e0, e1, lane, f0, f1, f2);
+    if (g < nv && lane < 3) {
+        const size_t i = (size_t)lane * nv + v;
+        double fk = K * (lane == 0 ? f0 : lane == 1 ? f1 : f2);
+        if (accumulate) fk += f[i];
+        f[i] = fk;
+    }
+}
+
+// One whole step for every vertex (forces from q, then the exclusive update) writing the new
+// positions to q_out, so that no vertex reads a position already advanced.  With take_f the
+// force field's contents join the spring forces and are cleared, as in the separate passes.
+template <int L, int U>
+__global__ __launch_bounds__(256) void k_spring_step(const int32_t *row, const int32_t *head, const double *rest,
+                                                     double K, const double *mass, double dt, const double *q,
+                                                     double *q_out, double *qd, double *f, int take_f, uint32_t nv) {
+    const uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    const uint32_t lane = threadIdx.x % L;
+    const uint32_t v = g < nv ? g : nv - 1;
+    const int32_t e0 = row[v], e1 = g < nv ? row[v + 1] : e0;
+    double f0, f1, f2;
+    spring_sum<L, U>(head, rest, q, nv, v, e0, e1, lane, f0, f1, f2);
+    if (g < nv && lane < 3) {
+        const size_t i = (size_t)lane * nv + v;
+        double fk = K * (lane == 0 ? f0 : lane == 1 ? f1 : f2);
+        if (take_f) {
+            fk += f[i];
+            f[i] = 0.0;
         }
-        f[v] = f0;
-        f[nv + v] = f1;
-        f[2 * nv + v] = f2;
+        integrate(q[i], qd[i], fk / mass[v], dt, q_out[i], qd[i]);
     }
 }
 
@@ -130,9 +185,7 @@ __global__ void k_spring_apply(const double *mass, double dt, double *q, double 
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
-            const double a = f[i] / m;
-            q[i] += qd[i] * dt + 0.5 * a * dt * dt;
-            qd[i] += a * dt;
+            integrate(q[i], qd[i], f[i] / m, dt, q[i], qd[i]);
             f[i] = 0.0;
         }
     }
@@ -171,8 +224,17 @@ __global__ __launch_bounds__(EN_THREADS) void k_kinetic_sum(const double *part, 
 
 void launch_forces(ebbx_springs_s *S, const double *q, double *f, int accumulate, hipStream_t s) {
     if (S->nv == 0) return;
-    hipLaunchKernelGGL(k_spring_forces, dim3(blocks_of(S->nv * LANES, 256)), dim3(256), 0, s, S->row.as<int32_t>(),
-                       S->head.as<int32_t>(), S->rest.as<double>(), S->K, q, f, (uint32_t)S->nv, accumulate);
+    hipLaunchKernelGGL((k_spring_forces<LANES, UNROLL>), dim3(blocks_of(S->nv * LANES, 256)), dim3(256), 0, s,
+                       S->row.as<int32_t>(), S->head.as<int32_t>(), S->rest.as<double>(), S->K, q, f,
+                       (uint32_t)S->nv, accumulate);
+    HIPCHK(hipGetLastError());
+}
+
+void launch_step(ebbx_springs_s *S, const double *mass, double dt, const double *q, double *q_out, double *qd,
+                 double *f, int take_f, hipStream_t s) {
+    hipLaunchKernelGGL((k_spring_step<LANES, UNROLL>), dim3(blocks_of(S->nv * LANES, 256)), dim3(256), 0, s,
+                       S->row.as<int32_t>(), S->head.as<int32_t>(), S->rest.as<double>(), S->K, mass, dt, q, q_out,
+                       qd, f, take_f, (uint32_t)S->nv);
     HIPCHK(hipGetLastError());
 }
 
@@ -181,6 +243,23 @@ void launch_apply(ebbx_springs_s *S, const double *mass, double dt, double *q, d
     hipLaunchKernelGGL(k_spring_apply, dim3(std::min<unsigned>(blocks_of(S->nv, 256), 16384)), dim3(256), 0, s, mass,
                        dt, q, qd, f, S->nv);
     HIPCHK(hipGetLastError());
+}
+
+// n steps ending with the positions in q: fused steps in pairs (q -> q2 -> q), the first of
+// them taking the force field's contents; an odd n starts with one step of the separate passes.
+void emit_steps(ebbx_springs_s *S, const double *mass, double dt, int32_t n, double *q, double *qd, double *force,
+                hipStream_t s) {
+    int32_t k = 0;
+    if (n % 2) {
+        launch_forces(S, q, force, 1, s);
+        launch_apply(S, mass, dt, q, qd, force, s);
+        k = 1;
+    }
+    double *q2 = S->q2.as<double>();
+    for (; k < n; k += 2) {
+        launch_step(S, mass, dt, q, q2, qd, force, k == 0, s);
+        launch_step(S, mass, dt, q2, q, qd, force, 0, s);
+    }
 }
 
 void check_vec(const void *p, const char *what, int64_t nv) {
@@ -307,14 +386,12 @@ extern "C" ebbx_status ebbx_springs_run(ebbx_springs sp, const double *mass, dou
         fail(EBBX_E_PHASE, "q, qd and force must not alias");
     if (nv == 0 || nsteps == 0) return EBBX_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (!S->q2.get()) S->q2.reset((size_t)(3 * nv) * sizeof(double), s);
     const void *key[4] = {mass, q, qd, force};
     if (nsteps >= RUN_CHUNK && (!S->exec || !std::equal(key, key + 4, S->key) || S->key_dt != dt)) {
         S->drop_graph();
         HIPCHK(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
-        for (int k = 0; k < RUN_CHUNK; ++k) {
-            launch_forces(S, q, force, 1, S->cap);
-            launch_apply(S, mass, dt, q, qd, force, S->cap);
-        }
+        emit_steps(S, mass, dt, RUN_CHUNK, q, qd, force, S->cap);
         HIPCHK(hipStreamEndCapture(S->cap, &S->graph));
         HIPCHK(hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0));
         std::copy(key, key + 4, S->key);
@@ -322,9 +399,6 @@ extern "C" ebbx_status ebbx_springs_run(ebbx_springs sp, const double *mass, dou
     }
     int32_t left = nsteps;
     for (; left >= RUN_CHUNK; left -= RUN_CHUNK) HIPCHK(hipGraphLaunch(S->exec, s));
-    for (; left > 0; --left) {
-        launch_forces(S, q, force, 1, s);
-        launch_apply(S, mass, dt, q, qd, force, s);
-    }
+    emit_steps(S, mass, dt, left, q, qd, force, s);
     EBBX_API_END
 }
