@@ -150,7 +150,6 @@ def bench_batch(stream, plain_rate):
     t0 = time.perf_counter()
     meshes, E, nu = mg.workload_batch()
     un = mg.union(meshes)
-    del meshes
     bm = ebbx.BatchMesh(un, E, nu, model=ebbx.NH, elem_prec=ebbx.F32)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
@@ -178,13 +177,64 @@ def bench_batch(stream, plain_rate):
     ms = min(times)
     useful = float(np.sum(nts * iters))
     rate = useful / (ms * 1e-3)
+    one = bench_one_by_one(stream, meshes[::8], E[::8], nu[::8])
     return {"meshes": bm.nm, "tets": bm.nt, "verts": bm.nv, "setup_s": round(setup, 1),
             "step_ms": round(ms, 3), "cg_iters_min": int(iters.min()), "cg_iters_max": int(iters.max()),
             "cg_iters_mean": round(float(iters.mean()), 2),
             "all_converged": bool(all(s.status == ebbx.OK for s in st)),
             "max_rel_res": max(s.rel_res for s in st),
             "tet_cg_iters_per_s": round(rate, 1),
-            "vs_plain_tet_cg_iters_per_s": round(rate / plain_rate, 4) if plain_rate else None}
+            "vs_plain_tet_cg_iters_per_s": round(rate / plain_rate, 4) if plain_rate else None,
+            "one_by_one": one,
+            "vs_one_by_one_tet_cg_iters_per_s": round(rate / one["tet_cg_iters_per_s"], 3)}
+
+
+def bench_one_by_one(stream, meshes, E, nu):
+    """The plain path on a sample of the batch's meshes, each its own Fem (block strategy, Morton
+    order, graph captured on its first step), stepped one after another with the batch's
+    per-mesh E, nu, tolerance and iteration cap: the work a caller without the batched entry
+    point would launch."""
+    import torch
+
+    from paper_1506_07577_amd import ebbx
+    fems, state = [], []
+    for m, Em, num in zip(meshes, E, nu):
+        fm = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.NH, elem_prec=ebbx.F32, E=float(Em), nu=float(num),
+                          strategy=ebbx.STRAT_BLOCK, morton=True)
+        z = torch.zeros(3, fm.nv, dtype=torch.float64, device="cuda")
+        fems.append(fm)
+        state.append((z, z.clone()))
+
+    def steps():
+        return [fm.fem.implicit_step(d, v, 1e-3, tol=1e-8, maxit=1000, stream=stream)
+                for fm, (d, v) in zip(fems, state)]
+
+    def reset():
+        for d, v in state:
+            d.zero_()
+            v.zero_()
+
+    steps()   # graph capture per mesh
+    best, st = None, None
+    for _ in range(3):
+        reset()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        out = steps()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        if best is None or t < best:
+            best, st = t, [ebbx.stats_fetch(o) for o in out]
+    useful = float(sum(fm.nt * s.iters for fm, s in zip(fems, st)))
+    res = {"meshes": len(fems), "tets": int(sum(fm.nt for fm in fems)), "ms": round(best, 3),
+           "all_converged": bool(all(s.status == ebbx.OK for s in st)),
+           "tet_cg_iters_per_s": round(useful / (best * 1e-3), 1),
+           "sample": "every 8th mesh of the batch (sides, E and nu as drawn)"}
+    for fm in fems:
+        fm.fem.close()
+    return res
 
 
 def bench_adjoint(stream, plain_rate):
