@@ -66,23 +66,43 @@ __device__ __forceinline__ double block_sum(double x, double *s4) {
 // iterations of that parity (the initial residual counts as parity 1).
 constexpr int PQ = 0, RR = 1, RZ = 2;
 
+// Each thread's share of a fixed-order sum over chunks [c0, c1): acc[s] += the partials at
+// offset o[s] of chunks c0 + t, c0 + t + VT, c0 + t + 2 VT, ... in that order.  The loads of
+// PART_BATCH strided chunks are issued before any of them is added, so a workgroup waits for
+// one round trip per batch rather than one per chunk; the order of the additions is unchanged.
+constexpr int PART_BATCH = 8;
+template <int NS>
+__device__ __forceinline__ void part_acc(const double *part, int c0, int c1, const int (&o)[NS], double (&acc)[NS]) {
+    for (int cb = c0 + (int)threadIdx.x; cb < c1; cb += PART_BATCH * VT) {
+        double l[PART_BATCH][NS];
+#pragma unroll
+        for (int j = 0; j < PART_BATCH; ++j) {
+            const int c = cb + j * VT;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) l[j][s] = c < c1 ? part[4 * c + o[s]] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < PART_BATCH; ++j)
+            if (cb + j * VT < c1)
+#pragma unroll
+                for (int s = 0; s < NS; ++s) acc[s] += l[j][s];
+    }
+}
+
 // Fixed-order sum of the partials at offset o of chunks [c0, c1).
 __device__ __forceinline__ double sum_parts(const double *part, int c0, int c1, int o, double *s4) {
-    double acc = 0.0;
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += VT) acc += part[4 * c + o];
-    return block_sum(acc, s4);
+    double acc[1] = {0.0};
+    part_acc<1>(part, c0, c1, {o}, acc);
+    return block_sum(acc[0], s4);
 }
 
 // Three fixed-order sums at once (offsets o0, o1, o2), each with exactly the
 // operation order of sum_parts, sharing the barriers.
 __device__ __forceinline__ void sum_parts3(const double *part, int c0, int c1, int o0, int o1, int o2, double *s12,
                                            double &r0, double &r1, double &r2) {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int c = c0 + (int)threadIdx.x; c < c1; c += VT) {
-        a0 += part[4 * c + o0];
-        a1 += part[4 * c + o1];
-        a2 += part[4 * c + o2];
-    }
+    double acc[3] = {0.0, 0.0, 0.0};
+    part_acc<3>(part, c0, c1, {o0, o1, o2}, acc);
+    double a0 = acc[0], a1 = acc[1], a2 = acc[2];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         a0 += __shfl_xor(a0, o, 64);
@@ -99,6 +119,27 @@ __device__ __forceinline__ void sum_parts3(const double *part, int c0, int c1, i
     r0 = (s12[0] + s12[1]) + (s12[2] + s12[3]);
     r1 = (s12[4] + s12[5]) + (s12[6] + s12[7]);
     r2 = (s12[8] + s12[9]) + (s12[10] + s12[11]);
+}
+
+// Two fixed-order sums at once (offsets o0, o1), as sum_parts3.
+__device__ __forceinline__ void sum_parts2(const double *part, int c0, int c1, int o0, int o1, double *s12, double &r0,
+                                           double &r1) {
+    double acc[2] = {0.0, 0.0};
+    part_acc<2>(part, c0, c1, {o0, o1}, acc);
+    double a0 = acc[0], a1 = acc[1];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a0 += __shfl_xor(a0, o, 64);
+        a1 += __shfl_xor(a1, o, 64);
+    }
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        s12[threadIdx.x >> 6] = a0;
+        s12[4 + (threadIdx.x >> 6)] = a1;
+    }
+    __syncthreads();
+    r0 = (s12[0] + s12[1]) + (s12[2] + s12[3]);
+    r1 = (s12[4] + s12[5]) + (s12[6] + s12[7]);
 }
 
 // One thread of the mesh's block marks mesh m finished.
@@ -370,8 +411,8 @@ __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGSta
             q[k] = w.q[i];
             dg[k] = w.diag[i];
         }
-    double pq, rz0, unused;
-    sum_parts3(part, ch.cptr[m], ch.cptr[m + 1], PQ, RZ + (par ^ 1), PQ, s12, pq, rz0, unused);
+    double pq, rz0;
+    sum_parts2(part, ch.cptr[m], ch.cptr[m + 1], PQ, RZ + (par ^ 1), s12, pq, rz0);
     const bool first = c == ch.cptr[m] && threadIdx.x == 0;
     if (!(pq > 0.0)) {   // breakdown: every workgroup of the mesh sees it and leaves x, r alone
         if (first) {
