@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint section")
     ap.add_argument("--no-assembled", action="store_true", help="skip the assembled-stiffness section")
     ap.add_argument("--no-springs", action="store_true", help="skip the spring-mass section")
+    ap.add_argument("--only", default="",
+                    help="locality workload: comma-separated order/strategy rows to run (e.g. morton/block)")
     return ap.parse_args()
 
 
@@ -290,7 +292,10 @@ def bench_locality(args):
     strat = {"atomic": (ebbx.STRAT_ATOMIC, 0), "seg": (ebbx.STRAT_SEG, 0), "block": (ebbx.STRAT_BLOCK, 0),
              "owner": (ebbx.STRAT_OWNER, 64)}
     rows = {}
+    only = {x for x in args.only.split(",") if x}
     for order in ("scrambled", "morton"):
+        if only and not any(x.startswith(order + "/") for x in only):
+            continue
         mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=w.model, elem_prec=ebbx.F64, E=w.E, nu=w.nu,
                             strategy=ebbx.STRAT_SEG, morton=(order == "morton"))
         d = mesh.to_dev(mg.perturbed_state(m, 0.02, seed=10))
@@ -298,6 +303,8 @@ def bench_locality(args):
         f = torch.empty_like(d)
         y = torch.empty_like(d)
         for name, (sid, blk) in strat.items():
+            if only and f"{order}/{name}" not in only:
+                continue
             mesh.fem.set_strategy(sid, blk)
             tf = time_events(lambda: (ebbx.cache_flush(1 << 30, stream), mesh.fem.forces(d, f, stream=stream)),
                              stream, 1)   # warm-up
