@@ -669,11 +669,12 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     // chunks of CG iterations; every kernel is predicated on its mesh's done flag,
     // the element map on the solve-wide all_done flag.  A fixed-count solve
     // (tol = 0) runs chunks of up to 128 without host checks.  With a tolerance
-    // the first chunk has 32 iterations and later ones 16, each launched only
-    // after the host has read that some mesh is still iterating: iterations
-    // past convergence cost a launch each, so the chunks stay short.
+    // the first chunk has 32 iterations and later ones 16 (8 for a batch, whose
+    // idle iterations still dispatch every block and chunk of every mesh), each
+    // launched only after the host has read that some mesh is still iterating:
+    // iterations past convergence cost a launch each, so the chunks stay short.
     S.first_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 32 : 128));
-    S.chunk_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 16 : 128));
+    S.chunk_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? (nm > 1 ? 8 : 16) : 128));
     // the fused kernels pick r.z slots by iteration parity: later chunks must start at even iterations
     if (p.maxit > S.first_iters && ((S.first_iters | S.chunk_iters) & 1))
         fail(EBBX_E_STATE, "CG chunk sizes must be even");
