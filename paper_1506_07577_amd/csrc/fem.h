@@ -37,6 +37,8 @@ struct ElemArgs {
     const uint32_t *slot[2];    // packed corner slots within the block (one or two words per tet)
     double *halo;               // partial sums of shared vertices, 3 per entry, block-major
     uint32_t nblk;              // tet blocks
+    uint32_t xcd_run_log2;      // 0: one contiguous range of blocks per XCD; k > 0: runs of 2^k
+                                // consecutive blocks dealt to the XCDs in turn
     // owner strategy: block b owns vertices [b*own_vb, (b+1)*own_vb) and evaluates every
     // tet incident to them (tets on a block boundary are evaluated by each block they touch)
     const int32_t *own_tptr;    // (nblk + 1) offsets into own_meta
