@@ -73,6 +73,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint section")
     ap.add_argument("--no-assembled", action="store_true", help="skip the assembled-stiffness section")
     ap.add_argument("--no-springs", action="store_true", help="skip the spring-mass section")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner section")
     ap.add_argument("--only", default="",
                     help="locality workload: comma-separated order/strategy rows to run (e.g. morton/block)")
     return ap.parse_args()
@@ -140,6 +141,35 @@ def bench_springs(stream, flush_bytes):
             "edge_evals_per_s": round(ne / (step_ms * 1e-3), 1),
             "step_algorithmic_bytes": step_bytes,
             "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def bench_autotune(stream, n):
+    """The autotuner on the headline mesh (64^3 neo-Hookean FP32, Morton order): every strategy
+    and block size timed on the stiffness product, the fastest kept; no cache."""
+    import torch
+
+    from paper_1506_07577_amd import ebbx
+    from paper_1506_07577_amd import meshgen as mg
+    w = mg.workload_plain(n)
+    m = w.mesh
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=w.model, elem_prec=ebbx.F32 if w.prec == "f32" else ebbx.F64,
+                        E=w.E, nu=w.nu, strategy=ebbx.STRAT_AUTO, morton=True)
+    d = mesh.to_dev(mg.perturbed_state(m, 0.02, seed=10))
+    u = mesh.to_dev(mg.direction(m, 11))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = mesh.fem.autotune(d, u, stream=stream)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    names = {ebbx.STRAT_ATOMIC: "atomic", ebbx.STRAT_SEG: "seg", ebbx.STRAT_BLOCK: "block",
+             ebbx.STRAT_BLOCK_LDS: "block_lds", ebbx.STRAT_OWNER: "owner"}
+    chosen = mesh.fem.get_strategy()
+    out = {"mesh": f"{n}^3 Morton", "tune_s": round(tune_s, 2),
+           "chosen": {"strategy": names.get(chosen[0], chosen[0]), "block": chosen[1]},
+           "candidates_us": {f"{names.get(sid, sid)}/{blk}": round(us, 2) for sid, blk, us in res},
+           "note": "stiffness product, warm calls timed by the tuner (5 after 2 warm-up, HIP events)"}
+    mesh.fem.close()
+    return out
 
 
 def bench_batch(stream, plain_rate):
@@ -557,6 +587,9 @@ def main():
     if not args.no_springs:
         extra["springs"] = bench_springs(stream, flush_bytes)
         log(f"springs: {extra['springs']['graph_step_us']} us per step")
+    if not args.no_autotune:
+        extra["autotune"] = bench_autotune(stream, args.n)
+        log(f"autotune: {extra['autotune']['chosen']} in {extra['autotune']['tune_s']} s")
     if not args.no_batch:
         extra["batched"] = bench_batch(stream, plain_rate)
         log(f"batched step {extra['batched']['step_ms']} ms")
