@@ -88,6 +88,26 @@ class DevBuf {
     Allocator a_;
 };
 
+// Ends a stream capture that an error left open, discarding the partial graph, so that the
+// capture stream stays usable for the next call; disarm() once the capture has been ended
+// the normal way.
+class CaptureGuard {
+  public:
+    explicit CaptureGuard(hipStream_t s) : s_(s) {}
+    ~CaptureGuard() {
+        if (!s_) return;
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(s_, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+    }
+    void disarm() { s_ = nullptr; }
+    CaptureGuard(const CaptureGuard &) = delete;
+    CaptureGuard &operator=(const CaptureGuard &) = delete;
+
+  private:
+    hipStream_t s_;
+};
+
 // ---- relational model ------------------------------------------------------
 
 struct Field {

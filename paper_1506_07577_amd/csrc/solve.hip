@@ -656,6 +656,7 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     hipStream_t cs = S.cap;
     // preamble: (step) forces and K v; Jacobi diagonal; rhs; initial residual
     capture_begin(cs);
+    CaptureGuard guard(cs);
     hipLaunchKernelGGL(k_step_begin, dim3((nm + VT - 1) / VT), dim3(VT), 0, cs, st, nm, ctl, n_inv);
     if (mode == 0) {
         elem_launch(F, OP_FORCE, S.w.dn, nullptr, S.w.f, 0, cs);
@@ -706,11 +707,14 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     // within it is one graph launch
     iterations(S.first_iters);
     HIPCHK(hipGetLastError());
+    guard.disarm();
     S.pre[mode] = capture_end(cs, &S.g_pre[mode]);
     if (!S.chunk && p.maxit > S.first_iters) {
         capture_begin(cs);
+        CaptureGuard chunk_guard(cs);
         iterations(S.chunk_iters);
         HIPCHK(hipGetLastError());
+        chunk_guard.disarm();
         S.chunk = capture_end(cs, &S.g_chunk);
     }
     S.valid = true;

@@ -391,7 +391,9 @@ extern "C" ebbx_status ebbx_springs_run(ebbx_springs sp, const double *mass, dou
     if (nsteps >= RUN_CHUNK && (!S->exec || !std::equal(key, key + 4, S->key) || S->key_dt != dt)) {
         S->drop_graph();
         HIPCHK(hipStreamBeginCapture(S->cap, hipStreamCaptureModeThreadLocal));
+        CaptureGuard guard(S->cap);
         emit_steps(S, mass, dt, RUN_CHUNK, q, qd, force, S->cap);
+        guard.disarm();
         HIPCHK(hipStreamEndCapture(S->cap, &S->graph));
         HIPCHK(hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0));
         std::copy(key, key + 4, S->key);
