@@ -178,6 +178,31 @@ def test_springs_full_size():
     sm.springs.close()
 
 
+def test_springs_wide_index_span():
+    """A scrambled 40^3 mesh (68,921 vertices, heads up to the whole index range away from their
+    tails): forces, then 34 steps (one captured chunk of fused steps and two direct ones) against
+    the oracle."""
+    m, _, _ = mg.scramble(mg.jitter(mg.kuhn_cube(40), 0.02, seed=21), seed=22)
+    tail, head = mg.directed_edges(m.tets, m.nv)
+    assert np.abs(head.astype(np.int64) - tail).max() > 32767
+    rng = np.random.default_rng(23)
+    mass = (1.0 + 0.5 * rng.uniform(-1, 1, m.nv)) / m.nv
+    q0 = m.X + (0.1 / 40) * rng.uniform(-1, 1, (m.nv, 3))
+    qd0 = 0.05 * rng.uniform(-1, 1, (m.nv, 3))
+    sm = ebbx.SpringMesh(m.X, tail, head, 1.3)
+    ref = oracle.Springs(m.X, tail, head, mass, 1.3)
+    assert nerr(sm.from_dev(sm.springs.forces(sm.to_dev(q0))), ref.forces(q0)) <= 1e-12
+    md = torch.as_tensor(mass).cuda()
+    q, qd = sm.to_dev(q0), sm.to_dev(qd0)
+    sm.springs.run(md, 1e-4, 34, q, qd, torch.zeros_like(q))
+    qs, qds = q0, qd0
+    for _ in range(34):
+        qs, qds = ref.step(qs, qds, 1e-4)
+    assert nerr(sm.from_dev(qd), qds) <= 1e-10
+    assert nerr(sm.from_dev(q) - q0, qs - q0) <= 1e-10
+    sm.springs.close()
+
+
 def test_randomized_springs():
     """Seeded sweep: 8 cubes of side 1..6 with shuffled (or sorted) edge rows, random K and dt:
     forces, then 20 steps (launched directly) or 40 (one captured chunk of 32 plus 8) against the
