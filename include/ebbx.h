@@ -358,7 +358,8 @@ ebbx_status ebbx_fem_edges_get(ebbx_fem fem, int32_t *row_ptr, int32_t *col, dou
  * (the example's per-edge kernel) and keeps row-ordered copies of the heads
  * and rest lengths: later changes to the relations do not affect the domain.
  * Synchronous.  K: the spring constant (finite).  Calls on one domain share
- * its scratch (energy partials, captured steps): order them on one stream. */
+ * its scratch (energy partials, the second position buffer and captured steps
+ * of ebbx_springs_run): order them on one stream. */
 ebbx_status ebbx_springs_create(ebbx_relation edges, const char *tail, const char *head, ebbx_relation verts,
                                 const char *pos_field, double K, ebbx_springs *out);
 ebbx_status ebbx_springs_destroy(ebbx_springs sp);
