@@ -74,6 +74,7 @@ def parse():
     ap.add_argument("--no-assembled", action="store_true", help="skip the assembled-stiffness section")
     ap.add_argument("--no-springs", action="store_true", help="skip the spring-mass section")
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner section")
+    ap.add_argument("--no-small", action="store_true", help="skip the 8^3 latency section")
     ap.add_argument("--only", default="",
                     help="locality workload: comma-separated order/strategy rows to run (e.g. morton/block)")
     return ap.parse_args()
@@ -141,6 +142,41 @@ def bench_springs(stream, flush_bytes):
             "edge_evals_per_s": round(ne / (step_ms * 1e-3), 1),
             "step_algorithmic_bytes": step_bytes,
             "step_hbm_frac": round(step_bytes / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def bench_small(stream):
+    """Latency on the small case (8^3 jittered cube, 3,072 tets, StVK FP64, bottom pinned): one
+    force call, one stiffness-product call (warm, medians of 50), and one implicit step with 50
+    CG iterations (dt = 1e-3, tol = 0) replayed from its graphs (median of 20)."""
+    import torch
+
+    from paper_1506_07577_amd import ebbx
+    from paper_1506_07577_amd import meshgen as mg
+    w = mg.workload_small()
+    m = w.mesh
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=w.model, elem_prec=ebbx.F64, E=w.E, nu=w.nu,
+                        strategy=ebbx.STRAT_BLOCK, morton=True)
+    d = mesh.to_dev(mg.perturbed_state(m, 0.02, seed=10))
+    u = mesh.to_dev(mg.direction(m, 11))
+    f, y = torch.empty_like(d), torch.empty_like(d)
+    tf = time_events(lambda: mesh.fem.forces(d, f, stream=stream), stream, 50)
+    tk = time_events(lambda: mesh.fem.kmul(d, u, y, stream=stream), stream, 50)
+    dd, vv = torch.zeros_like(d), torch.zeros_like(d)
+
+    def step():
+        mesh.fem.implicit_step(dd, vv, 1e-3, tol=0.0, maxit=w.maxit, stream=stream)
+
+    step()   # graph capture
+    ts = []
+    for _ in range(20):
+        dd.zero_()
+        vv.zero_()
+        ts += time_events(step, stream, 1)
+    mesh.fem.close()
+    return {"mesh": "8^3 jittered, 3072 tets, StVK FP64", "force_us": round(1e3 * statistics.median(tf), 2),
+            "kmul_us": round(1e3 * statistics.median(tk), 2),
+            "step_50_cg_iters_us": round(1e3 * statistics.median(ts), 1),
+            "note": "warm calls, HIP events per call (launch latency included); no roofline at this size"}
 
 
 def bench_autotune(stream, n):
@@ -587,6 +623,9 @@ def main():
     if not args.no_springs:
         extra["springs"] = bench_springs(stream, flush_bytes)
         log(f"springs: {extra['springs']['graph_step_us']} us per step")
+    if not args.no_small:
+        extra["small"] = bench_small(stream)
+        log(f"small: force {extra['small']['force_us']} us, step {extra['small']['step_50_cg_iters_us']} us")
     if not args.no_autotune:
         extra["autotune"] = bench_autotune(stream, args.n)
         log(f"autotune: {extra['autotune']['chosen']} in {extra['autotune']['tune_s']} s")
