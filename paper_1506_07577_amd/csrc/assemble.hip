@@ -10,7 +10,10 @@
 //  - k_elem_matrix: one thread per tet computes the tet's 12 x 12 stiffness in
 //    FP64, column by column (a unit displacement of corner b along axis k gives
 //    dF = e_k (x) grad N_b), with the element maps' own dP, and writes its
-//    sixteen 3x3 corner blocks to a per-tet record;
+//    sixteen 3x3 corner blocks to a per-tet record, one block column at a time
+//    through LDS so that the workgroup writes each tet's four blocks of that
+//    column (288 contiguous bytes) together (per-thread scattered stores of the
+//    record wrote 2.45x its bytes);
 //  - k_edge_gather: one thread per edge sums the corner blocks of the tets
 //    holding both of its vertices in ascending tet order (deterministic) and
 //    stores the edge block at the element precision, nine columns (SoA);
@@ -41,54 +44,70 @@ struct AsmArgs {
     const int32_t *tmesh;
 };
 
+constexpr int EM_THREADS = 128;   // tets per workgroup of the element-matrix kernel
+constexpr int EM_STRIDE = 37;     // LDS doubles per tet for one block column (36, padded)
+
+// Per-tet record: 144 doubles, block (a, b) (rows of corner a, columns of corner b) at
+// (4 b + a) * 9, row-major; so the four blocks of one column b are 36 contiguous doubles.
 template <class T, int MODEL>
-__global__ __launch_bounds__(256) void k_elem_matrix(AsmArgs a) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= a.nt) return;
-    double b[9];
+__global__ __launch_bounds__(EM_THREADS) void k_elem_matrix(AsmArgs a) {
+    __shared__ double s_col[EM_THREADS * EM_STRIDE];
+    const uint32_t t0 = blockIdx.x * EM_THREADS, t = t0 + threadIdx.x;
+    const bool in = t < a.nt;
+    const uint32_t nloc = min((uint32_t)EM_THREADS, a.nt - t0);   // tets of this workgroup
+    double b[9], G[9], gb[4][3], V0 = 1.0, mu = 0.0, lam = 0.0;
+    if (in) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) b[k] = (double)ldc<T>(a.B[k], t);
-    const double V0 = tet_V0(b);
-    const double mu = a.mu_t ? (double)ldc<T>(a.mu_t, t) : a.mu;
-    const double lam = a.lam_t ? (double)ldc<T>(a.lam_t, t) : a.lam;
-    double qd[4][3];
+        for (int k = 0; k < 9; ++k) b[k] = (double)ldc<T>(a.B[k], t);
+        V0 = tet_V0(b);
+        mu = a.mu_t ? (double)ldc<T>(a.mu_t, t) : a.mu;
+        lam = a.lam_t ? (double)ldc<T>(a.lam_t, t) : a.lam;
+        double qd[4][3];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const uint32_t v = (uint32_t)a.key[c][t];
+        for (int c = 0; c < 4; ++c) {
+            const uint32_t v = (uint32_t)a.key[c][t];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) qd[c][k] = a.d[k][v];
-    }
-    double G[9];
-    grad_from(qd, b, G);
-    // grad N_b: rows of B for corners 1..3, minus their sum for corner 0
-    double gb[4][3];
+            for (int k = 0; k < 3; ++k) qd[c][k] = a.d[k][v];
+        }
+        grad_from(qd, b, G);
+        // grad N_b: rows of B for corners 1..3, minus their sum for corner 0
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        gb[1][j] = b[j];
-        gb[2][j] = b[3 + j];
-        gb[3][j] = b[6 + j];
-        gb[0][j] = -(b[j] + b[3 + j] + b[6 + j]);
-    }
-    double *rec = a.ke + (size_t)t * 144;
-    bool ok = true;
-    for (int cb = 0; cb < 4; ++cb) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double dF[9], dP[9], h[12];
-#pragma unroll
-            for (int q = 0; q < 9; ++q) dF[q] = 0.0;
-            dF[3 * k] = gb[cb][0];
-            dF[3 * k + 1] = gb[cb][1];
-            dF[3 * k + 2] = gb[cb][2];
-            ok = dstress_scaled<double, MODEL>(mu, lam, V0, G, dF, dP) && ok;
-            corner_out(dP, b, h);   // h[3 a + r] = df_{a,r} / dd_{cb,k}
-#pragma unroll
-            for (int ca = 0; ca < 4; ++ca)
-#pragma unroll
-                for (int r = 0; r < 3; ++r) rec[(4 * ca + cb) * 9 + 3 * r + k] = h[3 * ca + r];
+        for (int j = 0; j < 3; ++j) {
+            gb[1][j] = b[j];
+            gb[2][j] = b[3 + j];
+            gb[3][j] = b[6 + j];
+            gb[0][j] = -(b[j] + b[3 + j] + b[6 + j]);
         }
     }
-    if (MODEL == EBBX_NH && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
+    bool ok = true;
+    // one block column at a time: every tet's 36 values go through LDS, then the workgroup
+    // writes each tet's 288 contiguous bytes of that column together
+    for (int cb = 0; cb < 4; ++cb) {
+        if (in) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                double dF[9], dP[9], h[12];
+#pragma unroll
+                for (int q = 0; q < 9; ++q) dF[q] = 0.0;
+                dF[3 * k] = gb[cb][0];
+                dF[3 * k + 1] = gb[cb][1];
+                dF[3 * k + 2] = gb[cb][2];
+                ok = dstress_scaled<double, MODEL>(mu, lam, V0, G, dF, dP) && ok;
+                corner_out(dP, b, h);   // h[3 a + r] = df_{a,r} / dd_{cb,k}
+#pragma unroll
+                for (int ca = 0; ca < 4; ++ca)
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) s_col[threadIdx.x * EM_STRIDE + ca * 9 + 3 * r + k] = h[3 * ca + r];
+            }
+        }
+        __syncthreads();
+        for (uint32_t e = threadIdx.x; e < nloc * 36u; e += EM_THREADS) {
+            const uint32_t i = e / 36u, o = e - 36u * i;
+            a.ke[(size_t)(t0 + i) * 144 + 36u * cb + o] = s_col[i * EM_STRIDE + o];
+        }
+        __syncthreads();
+    }
+    if (MODEL == EBBX_NH && in && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
 }
 
 // blocks[q][e] = sum over the edge's (tet, a, b) entries, in tet order, of ke block q
@@ -102,7 +121,8 @@ __global__ __launch_bounds__(256) void k_edge_gather(const double *ke, const int
     for (int q = 0; q < 9; ++q) s[q] = 0.0;
     const int32_t j0 = gptr[e], j1 = gptr[e + 1];
     for (int32_t j = j0; j < j1; ++j) {
-        const double *blk = ke + (size_t)gent[j] * 9;
+        const uint32_t c = gent[j];   // 16 t + 4 a + b: block (a, b) of tet t
+        const double *blk = ke + (size_t)(c >> 4) * 144 + (4u * (c & 3u) + ((c >> 2) & 3u)) * 9;
 #pragma unroll
         for (int q = 0; q < 9; ++q) s[q] += blk[q];
     }
@@ -230,9 +250,9 @@ template <class T> void launch_assemble(ebbx_fem_s *F, const double *d, hipStrea
         a.n_inv = F->status.as<unsigned long long>();
         a.tmesh = F->tmesh;
         if (F->model == EBBX_STVK)
-            hipLaunchKernelGGL((k_elem_matrix<T, EBBX_STVK>), dim3(grid_of(nt, 256)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_elem_matrix<T, EBBX_STVK>), dim3(grid_of(nt, EM_THREADS)), dim3(EM_THREADS), 0, s, a);
         else
-            hipLaunchKernelGGL((k_elem_matrix<T, EBBX_NH>), dim3(grid_of(nt, 256)), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_elem_matrix<T, EBBX_NH>), dim3(grid_of(nt, EM_THREADS)), dim3(EM_THREADS), 0, s, a);
         HIPCHK(hipGetLastError());
     }
     const int64_t ne = F->n_edges;
