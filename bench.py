@@ -100,16 +100,17 @@ def time_events(fn, stream, reps):
 
 
 def bench_springs(stream, flush_bytes):
-    """Spring-mass example on the 64^3 cube: force pass cold, and steps replayed from the graph."""
+    """Spring-mass example on the 64^3 cube (vertices and edges in Morton order): force pass cold,
+    and steps replayed from the graph."""
     import torch
 
     from paper_1506_07577_amd import ebbx
     from paper_1506_07577_amd import meshgen as mg
     w = mg.workload_springs(64)
     m = w.mesh
-    sm = ebbx.SpringMesh(m.X, w.tail, w.head, w.K)
+    sm = ebbx.SpringMesh(m.X, w.tail, w.head, w.K, morton=True)
     sp = sm.springs
-    md = torch.as_tensor(w.mass).cuda()
+    md = sm.scalar_to_dev(w.mass)
     q, qd = sm.to_dev(w.q0), sm.to_dev(w.qd0)
     f = torch.zeros_like(q)
     nv, ne = sm.nv, len(w.tail)

@@ -682,9 +682,11 @@ class Springs:
 class SpringMesh:
     """Convenience: verts (rest positions X) and edges (tail, head key-fields) relations, then Springs.
 
-    X: (nv, 3) float64; tail, head: (ne,) int32 (numpy or torch)."""
+    X: (nv, 3) float64; tail, head: (ne,) int32 (numpy or torch).  morton: reorder the vertices
+    (and the edges by tail) in Morton order first; to_dev / from_dev / scalar_to_dev then map
+    between the caller's vertex order and the library's."""
 
-    def __init__(self, X, tail, head, K):
+    def __init__(self, X, tail, head, K, morton=False):
         Xd = torch.as_tensor(X, dtype=torch.float64).t().contiguous().cuda()
         nv = Xd.shape[1]
         self.verts = Relation("verts", nv)
@@ -692,13 +694,33 @@ class SpringMesh:
         self.verts.bind_field("X", Xd)
         self.edges.bind_keyfield("tail", self.verts, torch.as_tensor(tail).to(torch.int32).contiguous().cuda())
         self.edges.bind_keyfield("head", self.verts, torch.as_tensor(head).to(torch.int32).contiguous().cuda())
+        self.vperm = None
+        if morton:
+            _codes, self.vperm, eperm = morton_order(self.verts, "X", self.edges, "tail")
+            self.verts.reorder(self.vperm)
+            self.edges.reorder(eperm)
         self.springs = Springs(self.edges, self.verts, K)
         self.nv = nv
 
-    @staticmethod
-    def to_dev(a):
-        return torch.as_tensor(a, dtype=torch.float64).t().contiguous().cuda()
+    def to_dev(self, a):
+        """(nv, 3) array in the caller's vertex order -> (3, nv) device tensor in library order."""
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if self.vperm is not None:
+            t = t[self.vperm.cpu().long()]
+        return t.t().contiguous().cuda()
 
-    @staticmethod
-    def from_dev(t):
-        return t.t().cpu().numpy()
+    def scalar_to_dev(self, a):
+        """(nv,) array (e.g. the masses) in the caller's vertex order -> device tensor in library order."""
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if self.vperm is not None:
+            t = t[self.vperm.cpu().long()]
+        return t.contiguous().cuda()
+
+    def from_dev(self, t):
+        """(3, nv) device tensor in library order -> (nv, 3) numpy in the caller's vertex order."""
+        a = t.t().cpu().numpy()
+        if self.vperm is not None:
+            out = a.copy()
+            out[self.vperm.cpu().numpy()] = a
+            return out
+        return a

@@ -203,6 +203,25 @@ def test_springs_wide_index_span():
     sm.springs.close()
 
 
+def test_springs_morton_order():
+    """The domain over Morton-ordered vertices and edges (the runtime's reorder of both
+    relations): forces and 40 steps against the oracle in the caller's order."""
+    m, tail, head, mass, q0, qd0, _sm, ref = _case(n=9, seed=31)
+    sm = ebbx.SpringMesh(m.X, tail, head, 1.0, morton=True)
+    assert sm.vperm is not None
+    assert nerr(sm.from_dev(sm.springs.forces(sm.to_dev(q0))), ref.forces(q0)) <= 1e-12
+    md = sm.scalar_to_dev(mass)
+    q, qd = sm.to_dev(q0), sm.to_dev(qd0)
+    sm.springs.run(md, 1e-4, 40, q, qd, torch.zeros_like(q))
+    qs, qds = q0, qd0
+    for _ in range(40):
+        qs, qds = ref.step(qs, qds, 1e-4)
+    assert nerr(sm.from_dev(qd), qds) <= 1e-10
+    assert nerr(sm.from_dev(q) - q0, qs - q0) <= 1e-10
+    sm.springs.close()
+    _sm.springs.close()
+
+
 def test_randomized_springs():
     """Seeded sweep: 8 cubes of side 1..6 with shuffled (or sorted) edge rows, random K and dt:
     forces, then 20 steps (launched directly) or 40 (one captured chunk of 32 plus 8) against the
