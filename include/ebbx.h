@@ -148,7 +148,10 @@ ebbx_status ebbx_morton_order(ebbx_relation verts, const char *pos_field, ebbx_r
 /* Permute rel in place by new_to_old_dev (a permutation of [0, size)): every
  * bound field and key-field of rel is gathered row-wise, and every key-field
  * of any live relation that targets rel is remapped through the inverse.
- * Groupings involving rel are dropped.  Synchronous. */
+ * Groupings involving rel are dropped.  EBBX_E_STATE (nothing permuted) if a
+ * live domain holds per-row data of rel: a FEM domain or batch union over rel
+ * as its tets or verts, a batch over rel as its meshes, a springs domain over
+ * rel as its edges or verts.  Synchronous. */
 ebbx_status ebbx_relation_reorder(ebbx_relation rel, const int32_t *new_to_old_dev);
 
 /* ---- the tet-FEM domain -------------------------------------------------- */
@@ -202,8 +205,8 @@ typedef struct {
  * m_v = sum of rho V0/4 over incident tets.  EBBX_E_DEGENERATE if a tet has
  * V0 <= 0.  Groups tets by keyfield if not yet grouped.  The FEM keeps views
  * of the key-field and the pinned field; reorder the relations (e.g. Morton)
- * before creating the domain, since a later ebbx_relation_reorder of tets or
- * verts leaves the domain's per-tet data in the old order.  Synchronous. */
+ * before creating the domain: while it lives, ebbx_relation_reorder of tets or
+ * verts fails with EBBX_E_STATE.  Synchronous. */
 ebbx_status ebbx_fem_create(ebbx_relation tets, const char *keyfield, ebbx_relation verts,
                             const char *pos_field, const char *pinned_field,
                             const ebbx_fem_params *params, ebbx_fem *out);

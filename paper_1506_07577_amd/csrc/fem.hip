@@ -42,10 +42,20 @@ void fem_unregister(ebbx_fem_s *F) {
     g_fems.erase(F);
 }
 
+const char *fem_relation_user(const ebbx_relation_s *r) {
+    std::lock_guard<std::mutex> lk(g_fem_mu);
+    for (const ebbx_fem_s *F : g_fems)
+        if (F->tets == r || F->verts == r) return F->batch_owned ? "the union domain of a batch" : "a FEM domain";
+    return nullptr;
+}
+
 // `block`: threads per workgroup for ATOMIC and SEG (64..256, multiple of 64);
 // tets per block for BLOCK (64, 128, 256, 512 or 1024).  0 = default.
 void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s) {
     if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_OWNER) fail(EBBX_E_ARG, "bad strategy %d", strategy);
+    // captured solver graphs hold pointers into the block, halo and owner tables that the
+    // table builders below free and reallocate: drop them whenever the strategy is set
+    step_drop_graphs(F);
     if (strategy == EBBX_STRAT_AUTO) strategy = EBBX_STRAT_BLOCK;
     if (strategy == EBBX_STRAT_OWNER) {
         int32_t vb = block ? block : (F->prec == EBBX_F32 ? 128 : 64);

@@ -158,4 +158,12 @@ void radix_sort_pairs_u64(uint64_t *keys, uint32_t *vals, int64_t n, int bits, h
 
 int current_device();
 
+// Whether a live domain holds per-row data of relation r in r's present order (a FEM
+// domain over r as its tets or verts, a batch over r as its meshes, a springs domain
+// over r as its edges or verts); those relations must not be reordered.  Each returns a
+// description of the first such domain, or NULL.
+const char *fem_relation_user(const ebbx_relation_s *r);
+const char *batch_relation_user(const ebbx_relation_s *r);
+const char *springs_relation_user(const ebbx_relation_s *r);
+
 }  // namespace ebbx

@@ -687,6 +687,10 @@ ebbx_status ebbx_relation_reorder(ebbx_relation rel, const int32_t *new_to_old_d
     const int64_t n = r->size;
     if (n == 0) return EBBX_OK;
     if (!new_to_old_dev) fail(EBBX_E_ARG, "permutation is NULL");
+    // a domain built over r keeps per-row copies (B, mass, tables, row-ordered edges) in
+    // r's present order: refuse rather than leave it silently inconsistent
+    for (const char *user : {fem_relation_user(r), batch_relation_user(r), springs_relation_user(r)})
+        if (user) fail(EBBX_E_STATE, "relation '%s' is in use by %s: destroy it before reordering", r->name.c_str(), user);
     hipStream_t s = nullptr;
     // validate: a permutation of [0, n)
     {

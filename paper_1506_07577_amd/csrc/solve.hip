@@ -907,6 +907,19 @@ ebbx_batch_s *check_batch(ebbx_batch b) {
     return b;
 }
 
+}  // namespace
+
+namespace ebbx {
+const char *batch_relation_user(const ebbx_relation_s *r) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (const ebbx_batch_s *B : g_batches)
+        if (B->meshes == r) return "a batch (its meshes relation)";
+    return nullptr;
+}
+}  // namespace ebbx
+
+namespace {
+
 KeyField &mesh_key(ebbx_relation_s *r, const char *name, ebbx_relation_s *meshes) {
     if (!name) fail(EBBX_E_ARG, "a mesh key-field name is NULL");
     KeyField &k = get_key(r, name);

@@ -24,6 +24,7 @@
 #include "fem.h"
 
 struct ebbx_springs_s {
+    const ebbx_relation_s *edges = nullptr, *verts = nullptr;   // the relations the row copies follow
     int64_t nv = 0, ne = 0;
     double K = 0.0;
     ebbx::DevBuf row;    // int32 (nv + 1): vertex v's edges are [row[v], row[v+1])
@@ -60,6 +61,17 @@ constexpr int EN_THREADS = 256;
 
 std::mutex g_mu;
 std::set<ebbx_springs_s *> g_springs;
+
+}  // namespace
+
+const char *springs_relation_user(const ebbx_relation_s *r) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const ebbx_springs_s *S : g_springs)
+        if (S->edges == r || S->verts == r) return "a springs domain";
+    return nullptr;
+}
+
+namespace {
 
 ebbx_springs_s *check_springs(ebbx_springs p) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -285,6 +297,8 @@ extern "C" ebbx_status ebbx_springs_create(ebbx_relation edges, const char *tail
     if (kt.arity != 1 || kh.arity != 1) fail(EBBX_E_SHAPE, "tail and head must have arity 1");
     const Field &X = get_field(vr, pos_field, EBBX_F64, 3);
     auto S = std::make_unique<ebbx_springs_s>();
+    S->edges = er;
+    S->verts = vr;
     S->nv = vr->size;
     S->ne = er->size;
     S->K = K;

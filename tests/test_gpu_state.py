@@ -1,0 +1,120 @@
+"""Domain state across calls: captured solver graphs after the scatter tables are rebuilt, and
+reorders of relations that a live domain depends on.
+
+Tolerance: FP64 element arithmetic, tolerance-free CG (50 fixed iterations on the 8^3 cube,
+which converges to round-off within them): 1e-10 normwise against the oracle.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1506_07577_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_1506_07577_amd import ebbx
+else:  # collected on a CPU host only to be deselected
+    ebbx = None
+
+
+def nerr(a, b):
+    s = np.abs(b).max()
+    return np.abs(a - b).max() / (s if s > 0 else 1.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    yield
+    torch.cuda.synchronize()
+
+
+def _two_oracle_steps(ref, d0, dt, maxit):
+    d1, v1, _dv, _s = ref.implicit_step(d0, np.zeros_like(d0), dt, tol=0.0, maxit=maxit)
+    d2, v2, _dv, _s = ref.implicit_step(d1, v1, dt, tol=0.0, maxit=maxit)
+    return (d1, v1), (d2, v2)
+
+
+@pytest.mark.parametrize("model", [ebbx.STVK if ebbx else 0, ebbx.NH if ebbx else 1])
+@pytest.mark.parametrize("between", ["block_sizes", "autotune", "owner"])
+def test_step_after_retune(model, between):
+    """step; change the block tables (BLOCK 128 then back to 256, or the autotuner, or the
+    owner strategy and back); step again: the second step must use the new tables, not graphs
+    captured over the freed ones."""
+    w = mg.workload_small()
+    m = w.mesh
+    ref = oracle.FEM.create(model, m.X, m.tets, w.E, w.nu, pinned=m.pinned)
+    d0 = mg.perturbed_state(m, 0.02, seed=10)
+    (d1, v1), (d2, v2) = _two_oracle_steps(ref, d0, w.dt, w.maxit)
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=model, elem_prec=ebbx.F64, E=w.E, nu=w.nu,
+                        strategy=ebbx.STRAT_BLOCK, block=256, morton=True)
+    dd, vv = mesh.to_dev(d0), mesh.to_dev(np.zeros_like(d0))
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(dd, vv, w.dt, tol=0.0, maxit=w.maxit))
+    assert s.status == ebbx.OK
+    assert nerr(mesh.from_dev(vv), v1) <= 1e-10 and nerr(mesh.from_dev(dd), d1) <= 1e-10
+    if between == "block_sizes":
+        mesh.fem.set_strategy(ebbx.STRAT_BLOCK, 128)
+        mesh.fem.set_strategy(ebbx.STRAT_BLOCK, 256)
+    elif between == "autotune":
+        mesh.fem.autotune(dd)
+    else:
+        mesh.fem.set_strategy(ebbx.STRAT_OWNER, 64)
+        mesh.fem.set_strategy(ebbx.STRAT_OWNER, 128)
+        mesh.fem.set_strategy(ebbx.STRAT_BLOCK, 256)
+    # the allocator may now hand the freed table memory to new tensors; zeros keep any stale
+    # index read in bounds while making stale results wrong
+    junk = [torch.zeros((1 << 16,), dtype=torch.float64, device="cuda") for _ in range(8)]
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(dd, vv, w.dt, tol=0.0, maxit=w.maxit))
+    assert s.status == ebbx.OK
+    assert nerr(mesh.from_dev(vv), v2) <= 1e-10 and nerr(mesh.from_dev(dd), d2) <= 1e-10
+    del junk
+    mesh.fem.close()
+
+
+def test_reorder_refused_while_a_domain_lives():
+    """A FEM domain keeps B, mass, pinned copies and block tables in the order of its relations:
+    reordering tets or verts under it is refused (nothing permuted); after the domain is
+    destroyed the same reorder goes through."""
+    m = mg.kuhn_cube(3)
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.STVK, elem_prec=ebbx.F64, strategy=ebbx.STRAT_BLOCK)
+    X0 = mesh.X.clone()
+    T0 = mesh.T.clone()
+    pv = torch.as_tensor(np.random.default_rng(3).permutation(m.nv).astype(np.int32)).cuda()
+    pt = torch.as_tensor(np.random.default_rng(4).permutation(m.nt).astype(np.int32)).cuda()
+    for rel, perm in ((mesh.verts, pv), (mesh.tets, pt)):
+        with pytest.raises(ebbx.EbbxError) as e:
+            rel.reorder(perm)
+        assert e.value.code == ebbx.E_STATE
+    assert torch.equal(mesh.X, X0) and torch.equal(mesh.T, T0)
+    # the domain still computes the un-permuted mesh
+    ref = oracle.FEM.create(ebbx.STVK, m.X, m.tets, 1e5, 0.3, pinned=m.pinned)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    assert nerr(mesh.from_dev(mesh.fem.forces(mesh.to_dev(d))), ref.forces(d)) <= 1e-10
+    mesh.fem.close()
+    mesh.verts.reorder(pv)
+    assert torch.equal(mesh.X, X0[:, pv.long()])
+
+
+def test_reorder_refused_under_springs_and_batch():
+    m = mg.kuhn_cube(2)
+    tail, head = mg.directed_edges(m.tets, m.nv)
+    sm = ebbx.SpringMesh(m.X, tail, head, K=1.0)
+    pv = torch.as_tensor(np.random.default_rng(5).permutation(m.nv).astype(np.int32)).cuda()
+    with pytest.raises(ebbx.EbbxError) as e:
+        sm.verts.reorder(pv)
+    assert e.value.code == ebbx.E_STATE
+    sm.springs.close()
+    sm.verts.reorder(pv)
+    un = mg.union([mg.kuhn_cube(2), mg.kuhn_cube(3)])
+    bm = ebbx.BatchMesh(un, np.array([1e5, 2e5]), np.array([0.3, 0.35]))
+    with pytest.raises(ebbx.EbbxError) as e:
+        bm.meshes.reorder(torch.tensor([1, 0], dtype=torch.int32, device="cuda"))
+    assert e.value.code == ebbx.E_STATE
+    with pytest.raises(ebbx.EbbxError) as e:
+        bm.verts.reorder(torch.arange(un.nv, dtype=torch.int32, device="cuda").flip(0).contiguous())
+    assert e.value.code == ebbx.E_STATE
+    bm.batch.close()

@@ -617,6 +617,45 @@ def test_spring_free_flight_and_energy():
     assert sp.kinetic_energy(qd) == pytest.approx(0.5 * np.sum(mass[:, None] * qd * qd), rel=1e-14)
 
 
+def test_kinetic_energy_worked_values():
+    # hand-computed: 1/2 * 2 * (1 + 4 + 4) + 1/2 * 0.5 * 16 = 9 + 4; a vertex at rest adds nothing
+    sp = oracle.Springs(np.zeros((3, 3)), [0], [1], np.array([2.0, 0.5, 7.0]), 1.0)
+    assert sp.kinetic_energy(np.array([[1.0, 2.0, -2.0], [0.0, 0.0, 4.0], [0.0, 0.0, 0.0]])) == 13.0
+    assert sp.kinetic_energy(np.zeros((3, 3))) == 0.0
+
+
+def test_kinetic_energy_conserved_by_the_two_mass_oscillator():
+    # Unequal masses on one spring along a direction with three nonzero components, plus a
+    # common drift.  The exact motion conserves KE + K (|q1 - q0| - L)^2 / 2 = K A^2 / 2 plus
+    # the drift energy M |V|^2 / 2; the relative part of KE vanishes at the turning points and
+    # equals K A^2 / 2 where the separation crosses L.  The explicit update follows this to
+    # O(dt) over a period, which a dropped factor, component or mass in the energy sum fails.
+    K, m, A, dt = 3.0, (2.0, 0.5), 0.01, 1e-4
+    n = np.array([1.0, 2.0, 2.0]) / 3.0
+    X = np.array([[0.0, 0.0, 0.0], n])
+    sp = oracle.Springs(X, [0, 1], [1, 0], np.array(m), K)
+    V = np.array([0.004, -0.006, 0.003])
+    q = np.array([[0.0, 0.0, 0.0], (1.0 + A) * n])
+    qd = np.tile(V, (2, 1))
+    drift = 0.5 * (m[0] + m[1]) * V.dot(V)
+    E0 = 0.5 * K * A * A + drift
+    w = np.sqrt(K * (1 / m[0] + 1 / m[1]))
+    steps = int(round(2 * np.pi / w / dt))
+    rel_ke = []
+    for _ in range(steps):
+        q, qd = sp.step(q, qd, dt)
+        ext = np.linalg.norm(q[1] - q[0]) - 1.0
+        E = sp.kinetic_energy(qd) + 0.5 * K * ext * ext
+        assert abs(E - E0) <= 2e-3 * E0
+        rel_ke.append(sp.kinetic_energy(qd) - drift)
+    rel_ke = np.array(rel_ke)
+    assert rel_ke.max() == pytest.approx(0.5 * K * A * A, rel=2e-3)
+    assert rel_ke.min() >= -1e-3 * 0.5 * K * A * A
+    # quarter period: crossing the rest length (maximum); half period: turning point (zero)
+    assert rel_ke[steps // 4] == pytest.approx(0.5 * K * A * A, rel=1e-2)
+    assert abs(rel_ke[steps // 2]) <= 1e-2 * 0.5 * K * A * A
+
+
 # --------------------------------------------------------------------------
 # Rayleigh damping (Vega's step computes damping with forces and stiffness:
 # Performance Evaluation); D = alpha M - beta K with K = df/dx
