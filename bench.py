@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--strategy", default="block", choices=["atomic", "seg", "block", "block_lds", "owner"])
+    ap.add_argument("--strategy", default="block", choices=["atomic", "seg", "block", "block_lds", "owner", "pipe"])
     ap.add_argument("--order", default="morton", choices=["lattice", "morton"])
     ap.add_argument("--n", type=int, default=64)
     ap.add_argument("--block", type=int, default=0,
@@ -424,7 +424,7 @@ def main():
     w = mg.workload_plain(args.n)
     m = w.mesh
     strat_id = {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-                "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER}
+                "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE}
     t_setup = time.perf_counter()
     mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=w.model, elem_prec=ebbx.F32, E=w.E, nu=w.nu,
                         strategy=strat_id[args.strategy], block=args.block, morton=(args.order == "morton"))

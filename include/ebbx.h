@@ -177,14 +177,25 @@ enum { EBBX_STVK = 0, EBBX_NH = 1 };
  *              touches; each owned vertex sums its incidences in the
  *              grouping's (tet, corner) order and is stored once: no halo,
  *              no atomics, one kernel, results bitwise equal to SEG;
+ *   PIPE:      as BLOCK with blocks of 256 tets, but one workgroup walks a
+ *              super-block of `block` consecutive blocks: while it evaluates
+ *              one block, the next block's vertex fields stream into LDS
+ *              (global-to-LDS loads), and each block vertex's sum is added
+ *              to an FP64 accumulator of the super-block, so only vertices
+ *              shared between super-blocks go through the halo pass (summed
+ *              in super-block order): no global atomics, bitwise
+ *              deterministic.  Needs at most 256 vertices per 256-tet block
+ *              (a Morton-ordered mesh) and at most 1023 per super-block
+ *              (EBBX_E_STATE / EBBX_E_ARG otherwise);
  *   AUTO:      BLOCK with 256 tets per block (ebbx_fem_autotune times the
  *              alternatives on the domain itself).
  * The `block` argument of the calls below is the workgroup size (threads) for
  * ATOMIC and SEG, the number of tets per block (64..1024, a power of two)
- * for BLOCK and BLOCK_LDS, and the owned vertices per block (64, 128 or
- * 256) for OWNER; 0 picks the default. */
+ * for BLOCK and BLOCK_LDS, the owned vertices per block (64, 128 or 256) for
+ * OWNER and the 256-tet blocks per workgroup (1..16) for PIPE; 0 picks the
+ * default (PIPE: 6, which on a Morton-ordered Kuhn mesh is 256 cells). */
 enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3,
-       EBBX_STRAT_BLOCK_LDS = 4, EBBX_STRAT_OWNER = 5 };
+       EBBX_STRAT_BLOCK_LDS = 4, EBBX_STRAT_OWNER = 5, EBBX_STRAT_PIPE = 6 };
 
 typedef struct {
     int32_t model;       /* EBBX_STVK or EBBX_NH */
@@ -315,6 +326,7 @@ typedef struct {
  * d and v alias; EBBX_E_STATE on the union domain of a batch. */
 ebbx_status ebbx_implicit_step(ebbx_fem fem, double *d, double *v, const ebbx_step_params *params,
                                ebbx_step_stats *stats_dev, ebbx_stream stream);
+
 
 /* ---- stiffness assembled on edges ---------------------------------------- */
 

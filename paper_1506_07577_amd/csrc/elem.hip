@@ -93,28 +93,6 @@ __global__ __launch_bounds__(256) void k_elem(ElemArgs a) {
 // that list (packed: 4 x 8 bits per word when every block has <= 256 vertices,
 // else 2 x 16 bits in each of two words).
 
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i on XCD i mod
-// 8), each XCD with its own L2.  Give XCD x one contiguous range of tet blocks,
-// so that neighbouring (Morton-adjacent) blocks, which share vertices, run under
-// the same L2.  A bijection of [0, nblk).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk) {
-    const uint32_t q = nblk >> 3, r = nblk & 7u, x = b & 7u, i = b >> 3;
-    return x * q + min(x, r) + i;
-}
-
-// The same with runs of 2^k consecutive blocks dealt to the XCDs in turn (k > 0),
-// for a batch: there the blocks still working late in a solve are those of the
-// few meshes that iterate longest, one contiguous stretch that a single range per
-// XCD would leave to one XCD.  Blocks past the last whole round of 8 runs keep the
-// contiguous mapping.  A bijection of [0, nblk).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk, uint32_t k) {
-    if (k == 0) return xcd_block(b, nblk);
-    const uint32_t full = (nblk >> (k + 3)) << (k + 3);
-    if (b >= full) return full + xcd_block(b - full, nblk - full);
-    const uint32_t x = b & 7u, i = b >> 3;
-    return ((((i >> k) << 3) + x) << k) + (i & ((1u << k) - 1u));
-}
-
 template <int W> __device__ __forceinline__ void unpack_slots(const ElemArgs &a, uint32_t t, uint32_t *s) {
     if (W == 1) {
         const uint32_t w = ldc<uint32_t>(a.slot[0], t);
@@ -165,34 +143,6 @@ __device__ __forceinline__ void reduce_slot(const ElemArgs &a, const T *s_h, uin
         hq[1] = a1;
         hq[2] = a2;
     }
-}
-
-// B = Dm^-1 and V0 = det(Dm)/6 of one tet from its corners' rest positions staged in
-// LDS (three columns of stride S): Dm from FP64 differences rounded to T, then the
-// adjugate over the determinant.  Recomputing B costs ~60 VALU per tet and saves the
-// 9 per-tet B values (36 B in FP32) of the stream.
-template <class T>
-__device__ __forceinline__ void rest_B(const double *s_x, uint32_t S, const uint32_t *sl, T *b, T &V0) {
-    double x0[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) x0[k] = s_x[k * S + sl[0]];
-    T Dm[9];
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) Dm[3 * k + c] = (T)(s_x[k * S + sl[c + 1]] - x0[k]);
-    const T det = det3(Dm);
-    const T idet = t_rcp(det);
-    b[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) * idet;
-    b[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) * idet;
-    b[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) * idet;
-    b[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) * idet;
-    b[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) * idet;
-    b[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) * idet;
-    b[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) * idet;
-    b[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) * idet;
-    b[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) * idet;
-    V0 = det * T(1.0 / 6.0);
 }
 
 // Gradient dD B of a vertex field staged in LDS (3 columns of S block vertices) over the
@@ -756,6 +706,27 @@ static size_t lds_limit() {
     return v > 0 ? (size_t)v : (size_t)64 * 1024;
 }
 
+// Sum each shared vertex's halo entries into out (the second pass of the block strategies).
+static void launch_halo(ebbx_fem_s *F, double *out, int accumulate, const int *skip, hipStream_t s) {
+    if (F->sh_n <= 0) return;
+    const int64_t nv = F->nv;
+    const dim3 g(grid_n(F->sh_n, 256, 1ll << 20));
+    const double *hl = (const double *)F->halo.get();
+    const int32_t *sv = F->sh_vert.as<int32_t>();
+    const int4 *tb = F->sh_tab.as<int4>();
+    const uint32_t sn = (uint32_t)F->sh_n;
+    switch (F->sh_nc) {
+    case 1: hipLaunchKernelGGL(k_halo_tab<1>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+    case 2: hipLaunchKernelGGL(k_halo_tab<2>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+    case 3: hipLaunchKernelGGL(k_halo_tab<3>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+    case 4: hipLaunchKernelGGL(k_halo_tab<4>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
+    default:
+        hipLaunchKernelGGL(k_halo_reduce, g, dim3(256), 0, s, hl, sv, F->sh_ptr.as<int32_t>(),
+                           F->sh_pos.as<int32_t>(), sn, out, out + nv, out + 2 * nv, accumulate, skip);
+    }
+    HIPCHK(hipGetLastError());
+}
+
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
                  hipStream_t s, const int *skip, const double *w, const int *mdone, bool finish_halo) {
     const int64_t nt = F->nt, nv = F->nv;
@@ -789,6 +760,15 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
         }
         return;
     }
+    if (F->strategy == EBBX_STRAT_PIPE) {
+        const size_t shmem = pipe_shmem(F, op);
+        if (shmem > lds_limit())
+            fail(EBBX_E_STATE, "pipelined blocks need %zu bytes of LDS per workgroup; use fewer blocks per "
+                 "workgroup", shmem);
+        launch_pipe(F, op, a, s);
+        if (finish_halo) launch_halo(F, out, accumulate, skip, s);
+        return;
+    }
     if (F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS) {
         const size_t shmem = block_shmem(F, op);
         if (shmem > lds_limit())
@@ -804,23 +784,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
             if (F->model == EBBX_STVK) launch_model<double, EBBX_STVK>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
             else launch_model<double, EBBX_NH>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
         }
-        if (F->sh_n > 0 && finish_halo) {
-            const dim3 g(grid_n(F->sh_n, 256, 1ll << 20));
-            const double *hl = (const double *)F->halo.get();
-            const int32_t *sv = F->sh_vert.as<int32_t>();
-            const int4 *tb = F->sh_tab.as<int4>();
-            const uint32_t sn = (uint32_t)F->sh_n;
-            switch (F->sh_nc) {
-            case 1: hipLaunchKernelGGL(k_halo_tab<1>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
-            case 2: hipLaunchKernelGGL(k_halo_tab<2>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
-            case 3: hipLaunchKernelGGL(k_halo_tab<3>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
-            case 4: hipLaunchKernelGGL(k_halo_tab<4>, g, dim3(256), 0, s, hl, sv, tb, sn, out, out + nv, out + 2 * nv, accumulate, skip); break;
-            default:
-                hipLaunchKernelGGL(k_halo_reduce, g, dim3(256), 0, s, hl, sv, F->sh_ptr.as<int32_t>(),
-                                   F->sh_pos.as<int32_t>(), sn, out, out + nv, out + 2 * nv, accumulate, skip);
-            }
-            HIPCHK(hipGetLastError());
-        }
+        if (finish_halo) launch_halo(F, out, accumulate, skip, s);
         return;
     }
     const int sc = F->strategy == EBBX_STRAT_SEG ? SC_PART : SC_ATOMIC;
@@ -1108,7 +1072,8 @@ int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hip
 
 HaloView elem_halo_view(const ebbx_fem_s *F) {
     HaloView h{};
-    const bool block = F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS;
+    const bool block = F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS ||
+                       F->strategy == EBBX_STRAT_PIPE;
     if (!block || F->sh_n == 0 || F->nt == 0) return h;
     h.row = F->sh_row.as<int32_t>();
     h.tab = F->sh_tab.as<int4>();
@@ -1124,27 +1089,20 @@ HaloView elem_halo_view(const ebbx_fem_s *F) {
 // Tets are cut into blocks of bt consecutive rows.  Per block: the sorted set of
 // vertices it touches, each corner's slot in that set, the block's incidences
 // ordered by (vertex, local tet, corner) with each corner's row in that order
-// and each vertex's run of rows, and where a vertex's sum goes: nowhere else if
-// the block holds every incident tet of the vertex (the block stores it),
-// otherwise a halo position.  Halo entries are block-major; the shared-vertex
-// table lists each vertex's entries in block order, and vertices that no tet
-// touches get an empty run, so the halo pass zeroes them.
-void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
-    const int64_t nt = F->nt, nv = F->nv;
-    if (bt != 64 && bt != 128 && bt != 256 && bt != 512 && bt != 1024)
-        fail(EBBX_E_ARG, "block strategy: tets per block must be 64, 128, 256, 512 or 1024 (got %d)", bt);
+// and each vertex's run of rows, and whether the block holds every incident tet
+// of the vertex.
+HostBlocks host_blocks(const std::vector<int32_t> &keys, const std::vector<int64_t> &rp, int64_t nt, int32_t bt) {
+    HostBlocks hb;
     const int64_t nblk = (nt + bt - 1) / bt;
-    std::vector<int32_t> keys((size_t)(4 * nt));
-    if (nt > 0) HIPCHK(hipMemcpy(keys.data(), F->keys, keys.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-    std::vector<int64_t> rp((size_t)(nv + 1));
-    HIPCHK(hipMemcpy(rp.data(), F->group->row_ptr.get(), rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
-    std::vector<int32_t> vptr((size_t)nblk + 1, 0), verts, lptr(1, 0);
-    std::vector<uint8_t> own;
+    hb.bt = bt;
+    hb.nblk = nblk;
+    hb.vptr.assign((size_t)nblk + 1, 0);
+    hb.lptr.assign(1, 0);
     std::vector<uint16_t> local((size_t)(4 * nt)), rowpos((size_t)(4 * nt));
     int64_t list_n = 0;   // incidence rows so far (all blocks)
-    verts.reserve((size_t)(nt + 16));
-    own.reserve((size_t)(nt + 16));
-    lptr.reserve((size_t)(nt + 16));
+    hb.verts.reserve((size_t)(nt + 16));
+    hb.own.reserve((size_t)(nt + 16));
+    hb.lptr.reserve((size_t)(nt + 16));
     std::vector<std::pair<int32_t, int32_t>> buf;   // (vertex, local tet * 4 + corner)
     int32_t maxv = 1;
     for (int64_t b = 0; b < nblk; ++b) {
@@ -1166,40 +1124,57 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
                 rowpos[(size_t)(c * nt + t0 + tl)] = (uint16_t)(list_n - list_b0);   // row in the block
                 ++list_n;
             }
-            verts.push_back(v);
-            lptr.push_back((int32_t)list_n);
-            own.push_back((int64_t)(j - i) == rp[(size_t)v + 1] - rp[(size_t)v] ? 1 : 0);
+            hb.verts.push_back(v);
+            hb.lptr.push_back((int32_t)list_n);
+            hb.own.push_back((int64_t)(j - i) == rp[(size_t)v + 1] - rp[(size_t)v] ? 1 : 0);
             ++nb;
             i = j;
         }
         maxv = std::max(maxv, nb);
-        vptr[(size_t)b + 1] = (int32_t)verts.size();
-        if (verts.size() >= (size_t)(1u << 31)) fail(EBBX_E_ARG, "block tables exceed int32");
+        hb.vptr[(size_t)b + 1] = (int32_t)hb.verts.size();
+        if (hb.verts.size() >= (size_t)(1u << 31)) fail(EBBX_E_ARG, "block tables exceed int32");
     }
     if (maxv > 65535) fail(EBBX_E_ARG, "a block touches %d vertices (limit 65535)", maxv);
     if (list_n >= (int64_t(1) << 31)) fail(EBBX_E_ARG, "block tables exceed int32");
+    hb.maxv = maxv;
     // per tet: the rows of its four corners in its block's incidence order
-    std::vector<uint32_t> pos((size_t)(2 * std::max<int64_t>(nt, 1)), 0u);
+    hb.pos.assign((size_t)(2 * std::max<int64_t>(nt, 1)), 0u);
     for (int64_t t = 0; t < nt; ++t) {
-        pos[(size_t)t] = (uint32_t)rowpos[(size_t)t] | ((uint32_t)rowpos[(size_t)(nt + t)] << 16);
-        pos[(size_t)(nt + t)] = (uint32_t)rowpos[(size_t)(2 * nt + t)] | ((uint32_t)rowpos[(size_t)(3 * nt + t)] << 16);
+        hb.pos[(size_t)t] = (uint32_t)rowpos[(size_t)t] | ((uint32_t)rowpos[(size_t)(nt + t)] << 16);
+        hb.pos[(size_t)(nt + t)] =
+            (uint32_t)rowpos[(size_t)(2 * nt + t)] | ((uint32_t)rowpos[(size_t)(3 * nt + t)] << 16);
     }
     // packed slots: 4 x 8 bits per word if every block has <= 256 vertices
     const int w = maxv <= 256 ? 1 : 2;
-    std::vector<uint32_t> packed((size_t)(w * std::max<int64_t>(nt, 1)), 0u);
+    hb.w = w;
+    hb.packed.assign((size_t)(w * std::max<int64_t>(nt, 1)), 0u);
     for (int64_t t = 0; t < nt; ++t) {
         const uint32_t s0 = local[(size_t)t], s1 = local[(size_t)(nt + t)], s2 = local[(size_t)(2 * nt + t)],
                        s3 = local[(size_t)(3 * nt + t)];
         if (w == 1) {
-            packed[(size_t)t] = s0 | (s1 << 8) | (s2 << 16) | (s3 << 24);
+            hb.packed[(size_t)t] = s0 | (s1 << 8) | (s2 << 16) | (s3 << 24);
         } else {
-            packed[(size_t)t] = s0 | (s1 << 16);
-            packed[(size_t)(nt + t)] = s2 | (s3 << 16);
+            hb.packed[(size_t)t] = s0 | (s1 << 16);
+            hb.packed[(size_t)(nt + t)] = s2 | (s3 << 16);
         }
     }
-    // halo entries are block-major (each block writes one contiguous run); every
-    // shared (or untouched) vertex lists its entries, which ascend in block order
-    std::vector<int32_t> hpos(verts.size(), -1);
+    return hb;
+}
+
+void upload(DevBuf &dst, const void *src, size_t bytes, hipStream_t s) {
+    dst.reset(std::max<size_t>(bytes, 16), s);
+    if (bytes) HIPCHK(hipMemcpy(dst.get(), src, bytes, hipMemcpyHostToDevice));
+}
+
+// Halo entries are unit-major (each unit writes one contiguous run); every
+// shared (or untouched) vertex lists its entries, which ascend in unit order,
+// and vertices that no tet touches get an empty run, so the halo pass zeroes
+// them.  verts/own: the vertex lists of the units (blocks or super-blocks) in
+// unit order; hpos receives each list entry's halo position or -1.
+void build_halo(ebbx_fem_s *F, const std::vector<int32_t> &verts, const std::vector<uint8_t> &own,
+                const std::vector<int64_t> &rp, std::vector<int32_t> &hpos, hipStream_t s) {
+    const int64_t nv = F->nv;
+    hpos.assign(verts.size(), -1);
     int32_t nh = 0;
     for (size_t p = 0; p < verts.size(); ++p)
         if (!own[p]) hpos[p] = nh++;
@@ -1221,49 +1196,15 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
             const int32_t r = row[(size_t)verts[p]];
             sh_pos[(size_t)(sh_ptr[(size_t)r] + fillc[(size_t)r]++)] = hpos[p];
         }
-    F->blk_tets = bt;
-    F->nblk = nblk;
-    F->blk_maxv = maxv;
-    F->blk_w = w;
-    F->blk_nverts = (int64_t)verts.size();
     F->sh_n = (int64_t)sh_vert.size();
     F->halo_n = (int64_t)nh;
-    auto up = [&](DevBuf &dst, const void *src, size_t bytes) {
-        dst.reset(std::max<size_t>(bytes, 8), s);
-        if (bytes) HIPCHK(hipMemcpy(dst.get(), src, bytes, hipMemcpyHostToDevice));
-    };
-    // fixed-stride copies: block b's vertices at [b*maxv, (b+1)*maxv), padded with -1,
-    // and its block-relative row starts at [b*(maxv+1), (b+1)*(maxv+1))
-    const size_t S = (size_t)maxv;
-    std::vector<int32_t> pverts((size_t)nblk * S, -1), phpos((size_t)nblk * S, -1);
-    std::vector<uint16_t> prow((size_t)nblk * (S + 1), 0);
-    for (int64_t b = 0; b < nblk; ++b) {
-        const int32_t a0 = vptr[(size_t)b], a1 = vptr[(size_t)b + 1];
-        const int32_t base = lptr[(size_t)a0], tot = lptr[(size_t)a1] - base;
-        for (size_t i = 0; i <= S; ++i) {
-            const int32_t k = a0 + (int32_t)i;
-            if (k < a1) {
-                pverts[(size_t)b * S + i] = verts[(size_t)k];
-                phpos[(size_t)b * S + i] = hpos[(size_t)k];
-                prow[(size_t)b * (S + 1) + i] = (uint16_t)(lptr[(size_t)k] - base);
-            } else {
-                prow[(size_t)b * (S + 1) + i] = (uint16_t)tot;
-            }
-        }
-    }
-    up(F->blk_vptr, vptr.data(), vptr.size() * sizeof(int32_t));
-    up(F->blk_verts, pverts.data(), pverts.size() * sizeof(int32_t));
-    up(F->blk_lptr, prow.data(), prow.size() * sizeof(uint16_t));
-    up(F->blk_pos, pos.data(), pos.size() * sizeof(uint32_t));
-    up(F->blk_hpos, phpos.data(), phpos.size() * sizeof(int32_t));
-    up(F->blk_local, packed.data(), packed.size() * sizeof(uint32_t));
-    up(F->sh_vert, sh_vert.data(), sh_vert.size() * sizeof(int32_t));
-    up(F->sh_ptr, sh_ptr.data(), sh_ptr.size() * sizeof(int32_t));
-    up(F->sh_pos, sh_pos.data(), sh_pos.size() * sizeof(int32_t));
-    // per vertex: its row in the shared-vertex table, or -1 (the block stores it)
+    upload(F->sh_vert, sh_vert.data(), sh_vert.size() * sizeof(int32_t), s);
+    upload(F->sh_ptr, sh_ptr.data(), sh_ptr.size() * sizeof(int32_t), s);
+    upload(F->sh_pos, sh_pos.data(), sh_pos.size() * sizeof(int32_t), s);
+    // per vertex: its row in the shared-vertex table, or -1 (a unit stores it)
     std::vector<int32_t> shrow((size_t)std::max<int64_t>(nv, 1), -1);
     for (size_t r = 0; r < sh_vert.size(); ++r) shrow[(size_t)sh_vert[r]] = (int32_t)r;
-    up(F->sh_row, shrow.data(), shrow.size() * sizeof(int32_t));
+    upload(F->sh_row, shrow.data(), shrow.size() * sizeof(int32_t), s);
     // fixed-width rows of halo positions when no vertex has more than 16 entries
     int32_t maxm = 0;
     for (size_t r = 0; r + 1 < sh_ptr.size(); ++r) maxm = std::max(maxm, sh_ptr[r + 1] - sh_ptr[r]);
@@ -1273,9 +1214,66 @@ void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
         std::vector<int32_t> tab(std::max<size_t>(sh_vert.size() * w, 4), -1);
         for (size_t r = 0; r < sh_vert.size(); ++r)
             for (int32_t j = sh_ptr[r]; j < sh_ptr[r + 1]; ++j) tab[r * w + (size_t)(j - sh_ptr[r])] = sh_pos[(size_t)j];
-        up(F->sh_tab, tab.data(), tab.size() * sizeof(int32_t));
+        upload(F->sh_tab, tab.data(), tab.size() * sizeof(int32_t), s);
     }
     F->halo.reset(std::max<size_t>((size_t)F->halo_n * 3 * sizeof(double), 8), s);
+}
+
+// Upload the block tables (without the halo): fixed-stride copies, block b's
+// vertices at [b*maxv, (b+1)*maxv) padded with -1 (halo positions hpos alike) and
+// its block-relative row starts at [b*(maxv+1), (b+1)*(maxv+1)); per tet the corner
+// rows and the packed slots.
+void upload_block_tables(ebbx_fem_s *F, const HostBlocks &hb, const std::vector<int32_t> &hpos, hipStream_t s) {
+    const int64_t nblk = hb.nblk;
+    const size_t S = (size_t)hb.maxv;
+    std::vector<int32_t> pverts((size_t)nblk * S, -1), phpos((size_t)nblk * S, -1);
+    std::vector<uint16_t> prow((size_t)nblk * (S + 1), 0);
+    for (int64_t b = 0; b < nblk; ++b) {
+        const int32_t a0 = hb.vptr[(size_t)b], a1 = hb.vptr[(size_t)b + 1];
+        const int32_t base = hb.lptr[(size_t)a0], tot = hb.lptr[(size_t)a1] - base;
+        for (size_t i = 0; i <= S; ++i) {
+            const int32_t k = a0 + (int32_t)i;
+            if (k < a1) {
+                pverts[(size_t)b * S + i] = hb.verts[(size_t)k];
+                if (!hpos.empty()) phpos[(size_t)b * S + i] = hpos[(size_t)k];
+                prow[(size_t)b * (S + 1) + i] = (uint16_t)(hb.lptr[(size_t)k] - base);
+            } else {
+                prow[(size_t)b * (S + 1) + i] = (uint16_t)tot;
+            }
+        }
+    }
+    upload(F->blk_vptr, hb.vptr.data(), hb.vptr.size() * sizeof(int32_t), s);
+    upload(F->blk_verts, pverts.data(), pverts.size() * sizeof(int32_t), s);
+    upload(F->blk_lptr, prow.data(), prow.size() * sizeof(uint16_t), s);
+    upload(F->blk_pos, hb.pos.data(), hb.pos.size() * sizeof(uint32_t), s);
+    upload(F->blk_hpos, phpos.data(), phpos.size() * sizeof(int32_t), s);
+    upload(F->blk_local, hb.packed.data(), hb.packed.size() * sizeof(uint32_t), s);
+    F->blk_tets = hb.bt;
+    F->nblk = nblk;
+    F->blk_maxv = hb.maxv;
+    F->blk_w = hb.w;
+    F->blk_nverts = (int64_t)hb.verts.size();
+}
+
+void download_keys(const ebbx_fem_s *F, std::vector<int32_t> &keys, std::vector<int64_t> &rp) {
+    keys.resize((size_t)(4 * F->nt));
+    if (F->nt > 0) HIPCHK(hipMemcpy(keys.data(), F->keys, keys.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    rp.resize((size_t)(F->nv + 1));
+    HIPCHK(hipMemcpy(rp.data(), F->group->row_ptr.get(), rp.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+}
+
+// The BLOCK tables with a halo of the blocks' shared vertices.
+void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
+    if (bt != 64 && bt != 128 && bt != 256 && bt != 512 && bt != 1024)
+        fail(EBBX_E_ARG, "block strategy: tets per block must be 64, 128, 256, 512 or 1024 (got %d)", bt);
+    std::vector<int32_t> keys;
+    std::vector<int64_t> rp;
+    download_keys(F, keys, rp);
+    const HostBlocks hb = host_blocks(keys, rp, F->nt, bt);
+    std::vector<int32_t> hpos;
+    build_halo(F, hb.verts, hb.own, rp, hpos, s);
+    upload_block_tables(F, hb, hpos, s);
+    F->halo_level = 0;
     F->blocks_built = true;
 }
 

@@ -37,6 +37,11 @@ struct ElemArgs {
     const uint32_t *slot[2];    // packed corner slots within the block (one or two words per tet)
     double *halo;               // partial sums of shared vertices, 3 per entry, block-major
     uint32_t nblk;              // tet blocks
+    // PIPE strategy
+    const uint32_t *blk_run;    // per block vertex (stride blk_stride): run start | run end << 11 | acc index << 22
+    const int32_t *sb_verts;    // per super-block (stride sb_stride): its vertices, -1 padded
+    const int32_t *sb_hpos;     // per super-block vertex: halo position, or -1 if the super-block owns it
+    uint32_t sb_g, nsb, sb_stride, stage_stride;
     uint32_t xcd_run_log2;      // 0: one contiguous range of blocks per XCD; k > 0: runs of 2^k
                                 // consecutive blocks dealt to the XCDs in turn
     // owner strategy: block b owns vertices [b*own_vb, (b+1)*own_vb) and evaluates every
@@ -85,8 +90,34 @@ void elem_energy(ebbx_fem_s *F, const double *d, double *out_dev, hipStream_t s)
 int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hipStream_t s);
 // Fill n doubles with a value (graph-safe, no memset node).
 void fill_f64(double *p, int64_t n, double v, hipStream_t s);
+// Host form of the tet-block tables (blocks of bt consecutive tets): per block its
+// sorted vertex list (CSR vptr/verts), each list entry's run of incidence rows
+// (global running starts lptr), whether the block holds every incident tet of the
+// entry's vertex (own), and per tet its corners' rows (pos, two 16-bit pairs) and
+// slots (packed, w words).
+struct HostBlocks {
+    int32_t bt = 0, maxv = 0, w = 1;
+    int64_t nblk = 0;
+    std::vector<int32_t> vptr, verts, lptr;
+    std::vector<uint8_t> own;
+    std::vector<uint32_t> pos, packed;
+};
+HostBlocks host_blocks(const std::vector<int32_t> &keys, const std::vector<int64_t> &rp, int64_t nt, int32_t bt);
+void download_keys(const ebbx_fem_s *F, std::vector<int32_t> &keys, std::vector<int64_t> &rp);
+void upload(DevBuf &dst, const void *src, size_t bytes, hipStream_t s);
+// Shared-vertex tables and halo buffer for units (blocks or super-blocks) whose vertex
+// lists, in unit order, are verts (own: the unit holds every incident tet).
+void build_halo(ebbx_fem_s *F, const std::vector<int32_t> &verts, const std::vector<uint8_t> &own,
+                const std::vector<int64_t> &rp, std::vector<int32_t> &hpos, hipStream_t s);
+void upload_block_tables(ebbx_fem_s *F, const HostBlocks &hb, const std::vector<int32_t> &hpos, hipStream_t s);
 // Build the tet-block tables of the BLOCK strategy.
 void build_blocks(ebbx_fem_s *F, int32_t tets_per_block, hipStream_t s);
+// Build the super-block tables of the PIPE strategy (blocks of 256 tets, g blocks per
+// super-block) and its halo.
+void build_pipe(ebbx_fem_s *F, int32_t g, hipStream_t s);
+// Launch the PIPE element kernel (pipe.hip); the halo pass is launched by the caller.
+void launch_pipe(ebbx_fem_s *F, ElemOp op, const ElemArgs &a, hipStream_t s);
+size_t pipe_shmem(const ebbx_fem_s *F, ElemOp op);
 // Build the vertex-owned block tables of the OWNER strategy.
 void build_owner(ebbx_fem_s *F, int32_t verts_per_block, hipStream_t s);
 // Assembled stiffness on edges (assemble.hip): the edges relation (once per
@@ -148,6 +179,14 @@ struct ebbx_fem_s {
         sh_row;
     int32_t sh_nc = 0;         // int4 chunks per row of sh_tab (0: use the CSR form)
     bool blocks_built = false;
+    int32_t halo_level = -1;   // the halo and shared-vertex tables are of: 0 blocks, g >= 1 super-blocks of
+                               // g blocks (PIPE), -1 none
+    // PIPE strategy: super-blocks of pipe_g consecutive 256-tet blocks
+    int32_t pipe_g = 0;
+    int64_t nsb = 0;
+    int32_t sb_maxv = 0;       // largest vertex count of one super-block (table stride)
+    int32_t stage_stride = 0;  // staged vertices per block in LDS (128 or 256)
+    ebbx::DevBuf blk_run, sb_verts, sb_hpos;
     // owner strategy tables
     int32_t own_vb = 0;        // owned vertices per block
     int64_t own_nblk = 0;

@@ -638,6 +638,75 @@ hipGraphExec_t capture_end(hipStream_t cap, hipGraph_t *g) {
     return ex;
 }
 
+// The buffers one solve runs on: the CG vectors, the chunk table of the mesh
+// segmentation, the chunk partials and the per-mesh state.
+struct SolveBufs {
+    StepVec w;
+    Chunks ch;
+    CGState *st;
+    SolveCtl *ctl;
+    double *part;
+    int nch, nm;
+    bool fused;
+};
+
+// The preamble of `mode` (0: step, 1: adjoint solve) onto stream cs: state reset, (step)
+// forces and K v, the Jacobi diagonal, the right-hand side and the initial residual.
+void launch_preamble(ebbx_fem_s *F, const ebbx_step_params &p, int mode, const SolveBufs &b, hipStream_t cs) {
+    const int64_t nv = F->nv;
+    unsigned long long *n_inv = F->status.as<unsigned long long>();
+    hipLaunchKernelGGL(k_step_begin, dim3((b.nm + VT - 1) / VT), dim3(VT), 0, cs, b.st, b.nm, b.ctl, n_inv);
+    if (mode == 0) {
+        elem_launch(F, OP_FORCE, b.w.dn, nullptr, b.w.f, 0, cs);
+        elem_launch(F, OP_KMUL, b.w.dn, b.w.vn, b.w.y, 0, cs);
+    }
+    if (p.precond == EBBX_PRECOND_JACOBI) elem_launch(F, OP_DIAG, b.w.dn, nullptr, b.w.diag, 0, cs);
+    hipLaunchKernelGGL(k_step_rhs, dim3(b.nch), dim3(VT), 0, cs, b.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
+                       nv, p.dt, p.g[0], p.g[1], p.g[2], p.alpha, p.beta, p.precond, mode, b.ch, b.part);
+    hipLaunchKernelGGL(k_step_init, dim3(b.nm), dim3(VT), 0, cs, b.st, (const double *)b.part, b.ch,
+                       (const unsigned long long *)n_inv, b.ctl);
+    HIPCHK(hipGetLastError());
+}
+
+// `count` CG iterations (at most maxit) onto stream cs, starting at an even iteration (the
+// fused kernels pick r.z slots by iteration parity).  Every kernel is predicated on its
+// mesh's done flag, the element map on the solve-wide all_done flag.
+void launch_iterations(ebbx_fem_s *F, const ebbx_step_params &p, const SolveBufs &b, int count, hipStream_t cs) {
+    const int64_t nv = F->nv;
+    // K p: a block-strategy element map leaves its shared vertices in the halo and
+    // k_cg_Ap finishes them as it reads y (one launch and one y round trip fewer)
+    const HaloView hv = elem_halo_view(F);
+    const double cm = 1.0 + p.dt * p.alpha, ck = p.dt * p.dt + p.dt * p.beta;
+    CGState *st = b.st;
+    SolveCtl *ctl = b.ctl;
+    double *part = b.part;
+    for (int it = 0; it < count && it < p.maxit; ++it) {
+        elem_launch(F, OP_KMUL, b.w.dn, b.w.p, b.w.y, 0, cs, &ctl->all_done, nullptr,
+                    b.nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr);
+        hipLaunchKernelGGL(k_cg_Ap, dim3(b.nch), dim3(VT), 0, cs, b.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
+                           nv, cm, ck, (const CGState *)st, b.ch, hv, part);
+        if (b.fused) {
+            const int par = it & 1;
+            hipLaunchKernelGGL(k_cg_update_f, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st, b.ch, part, par, ctl);
+            hipLaunchKernelGGL(k_cg_p_f, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st, b.ch, (const double *)part, par,
+                               p.tol, p.maxit, ctl);
+        } else {
+            hipLaunchKernelGGL(k_cg_alpha, dim3(b.nm), dim3(VT), 0, cs, st, (const double *)part, b.ch, ctl);
+            hipLaunchKernelGGL(k_cg_update, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, (const CGState *)st, b.ch, part);
+            hipLaunchKernelGGL(k_cg_beta, dim3(b.nm), dim3(VT), 0, cs, st, (const double *)part, b.ch, p.tol, p.maxit,
+                               ctl);
+            hipLaunchKernelGGL(k_cg_p, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, (const CGState *)st, b.ch);
+        }
+    }
+    HIPCHK(hipGetLastError());
+}
+
+SolveBufs step_bufs(ebbx_fem_s *F) {
+    auto &S = *F->step;
+    return SolveBufs{S.w, S.ch, S.state.as<CGState>(), S.ctl.as<SolveCtl>(), S.part.as<double>(), S.nch, S.nm,
+                     S.fused};
+}
+
 // Capture the preamble of `mode` (0: step, 1: adjoint solve) and, if the
 // parameters changed, the CG chunk shared by both.
 void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
@@ -647,73 +716,30 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
                       S.precond == p.precond && S.strategy == F->strategy && S.block == F->block && S.valid;
     if (!same) S.drop_graphs();
     if (S.pre[mode]) return;
-    const int64_t nv = F->nv;
-    const int nch = S.nch, nm = S.nm;
-    CGState *st = S.state.as<CGState>();
-    SolveCtl *ctl = S.ctl.as<SolveCtl>();
-    double *part = S.part.as<double>();
-    unsigned long long *n_inv = F->status.as<unsigned long long>();
+    const SolveBufs b = step_bufs(F);
     hipStream_t cs = S.cap;
-    // preamble: (step) forces and K v; Jacobi diagonal; rhs; initial residual
     capture_begin(cs);
     CaptureGuard guard(cs);
-    hipLaunchKernelGGL(k_step_begin, dim3((nm + VT - 1) / VT), dim3(VT), 0, cs, st, nm, ctl, n_inv);
-    if (mode == 0) {
-        elem_launch(F, OP_FORCE, S.w.dn, nullptr, S.w.f, 0, cs);
-        elem_launch(F, OP_KMUL, S.w.dn, S.w.vn, S.w.y, 0, cs);
-    }
-    if (p.precond == EBBX_PRECOND_JACOBI) elem_launch(F, OP_DIAG, S.w.dn, nullptr, S.w.diag, 0, cs);
-    hipLaunchKernelGGL(k_step_rhs, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(), nv,
-                       p.dt, p.g[0], p.g[1], p.g[2], p.alpha, p.beta, p.precond, mode, S.ch, part);
-    hipLaunchKernelGGL(k_step_init, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch,
-                       (const unsigned long long *)n_inv, ctl);
-    // chunks of CG iterations; every kernel is predicated on its mesh's done flag,
-    // the element map on the solve-wide all_done flag.  A fixed-count solve
-    // (tol = 0) runs chunks of up to 128 without host checks.  With a tolerance
-    // the first chunk has 32 iterations and later ones 16 (8 for a batch, whose
-    // idle iterations still dispatch every block and chunk of every mesh), each
-    // launched only after the host has read that some mesh is still iterating:
-    // iterations past convergence cost a launch each, so the chunks stay short.
+    launch_preamble(F, p, mode, b, cs);
+    // chunks of CG iterations.  A fixed-count solve (tol = 0) runs chunks of up to 128
+    // without host checks.  With a tolerance the first chunk has 32 iterations and later
+    // ones 16 (8 for a batch, whose idle iterations still dispatch every block and chunk of
+    // every mesh), each launched only after the host has read that some mesh is still
+    // iterating: iterations past convergence cost a launch each, so the chunks stay short.
     S.first_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? 32 : 128));
-    S.chunk_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? (nm > 1 ? 8 : 16) : 128));
+    S.chunk_iters = std::max(1, std::min(p.maxit, p.tol > 0.0 ? (b.nm > 1 ? 8 : 16) : 128));
     // the fused kernels pick r.z slots by iteration parity: later chunks must start at even iterations
     if (p.maxit > S.first_iters && ((S.first_iters | S.chunk_iters) & 1))
         fail(EBBX_E_STATE, "CG chunk sizes must be even");
-    // K p: a block-strategy element map leaves its shared vertices in the halo and
-    // k_cg_Ap finishes them as it reads y (one launch and one y round trip fewer)
-    const HaloView hv = elem_halo_view(F);
-    const double cm = 1.0 + p.dt * p.alpha, ck = p.dt * p.dt + p.dt * p.beta;
-    auto iterations = [&](int count) {
-        for (int it = 0; it < count && it < p.maxit; ++it) {
-            elem_launch(F, OP_KMUL, S.w.dn, S.w.p, S.w.y, 0, cs, &ctl->all_done, nullptr,
-                        nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr);
-            hipLaunchKernelGGL(k_cg_Ap, dim3(nch), dim3(VT), 0, cs, S.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
-                               nv, cm, ck, (const CGState *)st, S.ch, hv, part);
-            if (S.fused) {
-                const int par = it & 1;   // chunks after the first start at even iterations
-                hipLaunchKernelGGL(k_cg_update_f, dim3(nch), dim3(VT), 0, cs, S.w, nv, st, S.ch, part, par, ctl);
-                hipLaunchKernelGGL(k_cg_p_f, dim3(nch), dim3(VT), 0, cs, S.w, nv, st, S.ch, (const double *)part, par,
-                                   p.tol, p.maxit, ctl);
-            } else {
-                hipLaunchKernelGGL(k_cg_alpha, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, ctl);
-                hipLaunchKernelGGL(k_cg_update, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch, part);
-                hipLaunchKernelGGL(k_cg_beta, dim3(nm), dim3(VT), 0, cs, st, (const double *)part, S.ch, p.tol,
-                                   p.maxit, ctl);
-                hipLaunchKernelGGL(k_cg_p, dim3(nch), dim3(VT), 0, cs, S.w, nv, (const CGState *)st, S.ch);
-            }
-        }
-    };
     // the preamble graph also holds the first chunk, so a solve that converges
     // within it is one graph launch
-    iterations(S.first_iters);
-    HIPCHK(hipGetLastError());
+    launch_iterations(F, p, b, S.first_iters, cs);
     guard.disarm();
     S.pre[mode] = capture_end(cs, &S.g_pre[mode]);
     if (!S.chunk && p.maxit > S.first_iters) {
         capture_begin(cs);
         CaptureGuard chunk_guard(cs);
-        iterations(S.chunk_iters);
-        HIPCHK(hipGetLastError());
+        launch_iterations(F, p, b, S.chunk_iters, cs);
         chunk_guard.disarm();
         S.chunk = capture_end(cs, &S.g_chunk);
     }

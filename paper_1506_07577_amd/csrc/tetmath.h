@@ -343,6 +343,58 @@ template <class T, int MODEL> __device__ __forceinline__ bool diag12(T mu, T lam
     }
 }
 
+// ---- tet blocks -------------------------------------------------------------------
+
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i on XCD i mod
+// 8), each XCD with its own L2.  Give XCD x one contiguous range of tet blocks,
+// so that neighbouring (Morton-adjacent) blocks, which share vertices, run under
+// the same L2.  A bijection of [0, nblk).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk) {
+    const uint32_t q = nblk >> 3, r = nblk & 7u, x = b & 7u, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+// The same with runs of 2^k consecutive blocks dealt to the XCDs in turn (k > 0),
+// for a batch: there the blocks still working late in a solve are those of the
+// few meshes that iterate longest, one contiguous stretch that a single range per
+// XCD would leave to one XCD.  Blocks past the last whole round of 8 runs keep the
+// contiguous mapping.  A bijection of [0, nblk).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk, uint32_t k) {
+    if (k == 0) return xcd_block(b, nblk);
+    const uint32_t full = (nblk >> (k + 3)) << (k + 3);
+    if (b >= full) return full + xcd_block(b - full, nblk - full);
+    const uint32_t x = b & 7u, i = b >> 3;
+    return ((((i >> k) << 3) + x) << k) + (i & ((1u << k) - 1u));
+}
+
+// B = Dm^-1 and V0 = det(Dm)/6 of one tet from its corners' rest positions staged in
+// LDS (three columns of stride S): Dm from FP64 differences rounded to T, then the
+// adjugate over the determinant.  Recomputing B costs ~60 VALU per tet and saves the
+// 9 per-tet B values (36 B in FP32) of the stream.
+template <class T>
+__device__ __forceinline__ void rest_B(const double *s_x, uint32_t S, const uint32_t *sl, T *b, T &V0) {
+    double x0[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x0[k] = s_x[k * S + sl[0]];
+    T Dm[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Dm[3 * k + c] = (T)(s_x[k * S + sl[c + 1]] - x0[k]);
+    const T det = det3(Dm);
+    const T idet = t_rcp(det);
+    b[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) * idet;
+    b[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) * idet;
+    b[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) * idet;
+    b[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) * idet;
+    b[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) * idet;
+    b[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) * idet;
+    b[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) * idet;
+    b[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) * idet;
+    b[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) * idet;
+    V0 = det * T(1.0 / 6.0);
+}
+
 // ---- gather / element evaluation ----------------------------------------------------
 
 // M = dD B with dD = [q1-q0 | q2-q0 | q3-q0]; differences in FP64, then rounded to T

@@ -40,7 +40,7 @@ def _gpu():
 
 def _strat(name):
     return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER}[name]
+            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE}[name]
 
 
 def _pair(m, model, E_tet, nu=0.3, prec="f64", strategy="block"):
@@ -67,7 +67,7 @@ MODELS = [("stvk", oracle.STVK), ("nh", oracle.NH)]
 # single evaluations
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("strategy", ["atomic", "seg", "block", "block_lds", "owner"])
+@pytest.mark.parametrize("strategy", ["atomic", "seg", "block", "block_lds", "owner", "pipe"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("mname,model", MODELS)
 def test_tmul_parity(mname, model, prec, strategy):
@@ -326,7 +326,7 @@ def test_step_vjp_full_size_vs_oracle():
 # vector-Jacobian products of the element maps
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("strategy", ["atomic", "block", "owner"])
+@pytest.mark.parametrize("strategy", ["atomic", "block", "owner", "pipe"])
 @pytest.mark.parametrize("mname,model", MODELS)
 def test_forces_and_kmul_vjp(mname, model, strategy):
     m = mg.jitter(mg.kuhn_cube(2), 0.01, seed=0)

@@ -39,7 +39,7 @@ def _gpu():
 
 def _strat(name):
     return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER}[name]
+            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE}[name]
 
 
 def _pair(m, model, prec, strat, E=1e5, nu=0.3, E_tet=None, morton=False):
@@ -50,13 +50,13 @@ def _pair(m, model, prec, strat, E=1e5, nu=0.3, E_tet=None, morton=False):
     return mesh, ref
 
 
-@pytest.mark.parametrize("strat", ["atomic", "seg", "block", "owner"])
+@pytest.mark.parametrize("strat", ["atomic", "seg", "block", "owner", "pipe"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("model", [0, 1])
 def test_damped_step_parity(model, prec, strat):
     """7^3 cube, jittered, from a perturbed state with a velocity: two fixed-count damped steps."""
     m = mg.jitter(mg.kuhn_cube(7), 0.01, seed=3)
-    mesh, ref = _pair(m, model, prec, strat, E=2e5, nu=0.35, morton=(strat == "block"))
+    mesh, ref = _pair(m, model, prec, strat, E=2e5, nu=0.35, morton=(strat in ("block", "pipe")))
     d0 = mg.perturbed_state(m, 0.01, seed=10)
     v0 = 0.1 * mg.direction(m, 11)
     d, v = mesh.to_dev(d0), mesh.to_dev(v0)

@@ -40,7 +40,7 @@ def _two_oracle_steps(ref, d0, dt, maxit):
 
 
 @pytest.mark.parametrize("model", [ebbx.STVK if ebbx else 0, ebbx.NH if ebbx else 1])
-@pytest.mark.parametrize("between", ["block_sizes", "autotune", "owner"])
+@pytest.mark.parametrize("between", ["block_sizes", "autotune", "owner", "pipe"])
 def test_step_after_retune(model, between):
     """step; change the block tables (BLOCK 128 then back to 256, or the autotuner, or the
     owner strategy and back); step again: the second step must use the new tables, not graphs
@@ -61,6 +61,9 @@ def test_step_after_retune(model, between):
         mesh.fem.set_strategy(ebbx.STRAT_BLOCK, 256)
     elif between == "autotune":
         mesh.fem.autotune(dd)
+    elif between == "pipe":
+        mesh.fem.set_strategy(ebbx.STRAT_PIPE, 2)
+        mesh.fem.set_strategy(ebbx.STRAT_BLOCK, 256)
     else:
         mesh.fem.set_strategy(ebbx.STRAT_OWNER, 64)
         mesh.fem.set_strategy(ebbx.STRAT_OWNER, 128)
