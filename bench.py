@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-springs", action="store_true", help="skip the spring-mass section")
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner section")
     ap.add_argument("--no-small", action="store_true", help="skip the 8^3 latency section")
+    ap.add_argument("--no-cpu-adjoint", action="store_true", help="skip the oracle's adjoint sample")
+    ap.add_argument("--no-cpu-batch", action="store_true", help="skip the oracle's 16-mesh batch sample")
     ap.add_argument("--only", default="",
                     help="locality workload: comma-separated order/strategy rows to run (e.g. morton/block)")
     return ap.parse_args()
@@ -306,7 +308,7 @@ def bench_one_by_one(stream, meshes, E, nu):
     return res
 
 
-def bench_adjoint(stream, plain_rate):
+def bench_adjoint(stream, plain_step_rate):
     """48^3 cube, neo-Hookean FP64, per-tet log-normal E: 20 implicit steps (CG to 1e-10)
     forward, then dL/dE and dL/dd0 of ||x_T - target||^2 with checkpoints every 5 steps."""
     import torch
@@ -339,9 +341,17 @@ def bench_adjoint(stream, plain_rate):
 
     run()   # graph capture
     fw, bw = min(run() for _ in range(3))
+    fwd_rate = mesh.nt * 20 / fw
     return {"tets": mesh.nt, "verts": mesh.nv, "steps": 20, "checkpoint_every": 5,
             "forward_ms": round(1e3 * fw, 2), "backward_ms": round(1e3 * bw, 2),
             "backward_over_forward": round(bw / fw, 3),
+            "forward_backward_over_forward": round((fw + bw) / fw, 3),
+            "forward_tet_steps_per_s": round(fwd_rate, 1),
+            "forward_backward_tet_steps_per_s": round(mesh.nt * 20 / (fw + bw), 1),
+            "plain_step_tet_steps_per_s": round(plain_step_rate, 1) if plain_step_rate else None,
+            "forward_vs_plain_step": round(fwd_rate / plain_step_rate, 3) if plain_step_rate else None,
+            "vs_plain_note": "plain = one 64^3 NH FP32 step with 100 fixed CG iterations on the same GPU; the "
+                             "adjoint's steps are FP64 and stop at 1e-10 (different iteration counts)",
             "note": "wall clock with device syncs; forward = 20 implicit steps (CG to 1e-10), backward = "
                     "segment recompute + 20 step VJPs (adjoint CG, K w, T[v, w], dL/dE)"}
 
@@ -397,6 +407,141 @@ def bench_locality(args):
                        f"mean of {args.steps} calls",
            "algorithmic_bytes_kmul": canonical_bytes(m.nt, m.nv, "kmul", 8), "rows": rows}
     print(json.dumps(out), flush=True)
+
+
+def host_cpu():
+    """(threads for the oracle, CPU model): the cores this process may run on, capped by
+    OMP_NUM_THREADS when set (the machine's CPU share), and /proc/cpuinfo's model name."""
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        cores = min(cores, int(omp))
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return cores, model
+
+
+def timed(fn, seconds, min_reps=1):
+    """(repetitions, elapsed s) of fn run until `seconds` have passed (at least min_reps)."""
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if reps >= min_reps and el >= seconds:
+            return reps, el
+
+
+def cpu_baseline(args, w, m, nt, extra):
+    """The oracle timed on this host's cores beside the GPU rows, on bounded samples of the same
+    workloads.  The headline value is the oracle's force + K u on `cores` OpenMP threads (per-corner
+    partials, then a vertex gather over the grouping: bit-for-bit the serial oracle's result); the
+    serial figure and the other rows are the serial oracle as the tests use it."""
+    import oracle
+    from paper_1506_07577_amd import meshgen as mg
+    cores, model = host_cpu()
+    ref = oracle.FEM.create(w.model, m.X, m.tets, w.E, w.nu, pinned=m.pinned)
+    dh = mg.perturbed_state(m, 0.02, seed=10)
+    uh = mg.direction(m, 11)
+    ref.kmul_mt(dh, uh, cores)   # builds the grouping once
+    sec = args.cpu_seconds
+    reps, el = timed(lambda: (ref.forces_mt(dh, cores), ref.kmul_mt(dh, uh, cores)), 0.35 * sec)
+    cpu = {"value": round(reps * nt / el, 1), "unit": "tet force+Kmul evals/s", "cores": cores,
+           "kind": "oracle", "cpu_model": model,
+           "sample": f"{reps} force+Kmul passes over the full {nt}-tet mesh (FP64 C oracle, OpenMP over "
+                     f"tets then a vertex gather, {cores} threads) in {el:.1f} s"}
+    rows = {}
+    reps1, el1 = timed(lambda: (ref.forces(dh), ref.kmul(dh, uh)), 0.25 * sec)
+    rows["single_thread"] = {"value": round(reps1 * nt / el1, 1), "unit": "tet force+Kmul evals/s",
+                             "cores": 1, "sample": f"{reps1} serial passes, full mesh, {el1:.1f} s"}
+    # one implicit step: the per-iteration cost from two iteration counts (the force, K v and
+    # diagonal passes of the step's setup cancel)
+    t = []
+    for it in (2, 5):
+        t0 = time.perf_counter()
+        ref.implicit_step(dh, np.zeros_like(dh), w.dt, tol=0.0, maxit=it)
+        t.append(time.perf_counter() - t0)
+    per_it = max((t[1] - t[0]) / 3.0, 1e-9)
+    rows["implicit_step"] = {"value": round(nt / per_it, 1), "unit": "tet CG iterations/s",
+                             "sample": f"full mesh, serial; (t(5 iterations) - t(2 iterations)) / 3 = "
+                                       f"{1e3 * per_it:.0f} ms per iteration, setup passes excluded"}
+    if "implicit_step" in extra:
+        rows["implicit_step"]["gpu_over_oracle"] = round(
+            extra["implicit_step"]["tet_cg_iters_per_s"] / rows["implicit_step"]["value"], 1)
+    if "assembled" in extra:
+        rp, col = oracle.edges(m.nv, m.tets)
+        blocks = ref.assemble(dh, rp, col)
+        t0 = time.perf_counter()
+        for _ in range(5):
+            oracle.spmv(rp, col, blocks, uh)
+        el = time.perf_counter() - t0
+        rows["assembled_spmv"] = {"value": round(5 * nt / el, 1), "unit": "tet-equivalent products/s",
+                                  "sample": f"5 block-CSR products, full mesh, serial, {el:.2f} s"}
+        rows["assembled_spmv"]["gpu_over_oracle"] = round(
+            (nt / (extra["assembled"]["spmv_us"] * 1e-6)) / rows["assembled_spmv"]["value"], 1)
+    if "springs" in extra:
+        sw = mg.workload_springs(64)
+        sref = oracle.Springs(sw.mesh.X, sw.tail, sw.head, sw.mass, sw.K)
+        q1, qd1 = sw.q0, sw.qd0
+        t0 = time.perf_counter()
+        for _ in range(5):
+            q1, qd1 = sref.step(q1, qd1, sw.dt)
+        el = time.perf_counter() - t0
+        rows["springs"] = {"value": round(5 * len(sw.tail) / el, 1), "unit": "spring evals/s",
+                           "sample": f"5 steps, full 64^3 edge set, serial, {el:.2f} s"}
+        rows["springs"]["gpu_over_oracle"] = round(extra["springs"]["edge_evals_per_s"] /
+                                                   rows["springs"]["value"], 1)
+    if "adjoint" in extra and not args.no_cpu_adjoint:
+        # the 48^3 adjoint workload, first step only: forward (CG to 1e-10) and its step VJP
+        ma = mg.kuhn_cube(48)
+        E_tet, target, _ = mg.adjoint_recipe(ma, seed=2)
+        aref = oracle.FEM.create(oracle.NH, ma.X, ma.tets, E_tet, 0.3, pinned=ma.pinned)
+        z = np.zeros((ma.nv, 3))
+        t0 = time.perf_counter()
+        d1, v1, _dv, so = aref.implicit_step(z, z, 1e-3, tol=1e-10, maxit=2000)
+        t1 = time.perf_counter()
+        aref.step_vjp(z, v1, 2.0 * (d1 + ma.X - target), np.zeros_like(z), 1e-3, tol=1e-10, maxit=2000)
+        t2 = time.perf_counter()
+        steps = extra["adjoint"]["steps"]
+        fw_est, bw_est = steps * (t1 - t0), steps * (t2 - t1)
+        rows["adjoint"] = {
+            "forward_tet_steps_per_s": round(ma.nt / (t1 - t0), 1),
+            "forward_backward_tet_steps_per_s": round(ma.nt / (t2 - t0), 1),
+            "unit": "tet steps/s",
+            "forward_s_extrapolated": round(fw_est, 2), "backward_s_extrapolated": round(bw_est, 2),
+            "sample": f"first of the {steps} steps only (forward {so.iters} CG iterations to 1e-10, then its "
+                      f"step VJP; no checkpoint recompute), serial, {t2 - t0:.1f} s; the extrapolated "
+                      f"times are {steps} x the sampled step",
+            "gpu_over_oracle_forward": round(extra["adjoint"]["forward_tet_steps_per_s"] /
+                                             (ma.nt / (t1 - t0)), 1)}
+    if "batched" in extra and not args.no_cpu_batch:
+        # 16 meshes of the batch (every 16th, sides, E and nu as drawn), one step each, CG to 1e-8
+        meshes, E, nu = mg.workload_batch()
+        sel = list(range(0, len(meshes), 16))
+        useful, el = 0.0, 0.0
+        for i in sel:
+            mm = meshes[i]
+            bref = oracle.FEM.create(oracle.NH, mm.X, mm.tets, float(E[i]), float(nu[i]), pinned=mm.pinned)
+            z = np.zeros((mm.nv, 3))
+            t0 = time.perf_counter()
+            _d1, _v1, _dv, so = bref.implicit_step(z, z, 1e-3, tol=1e-8, maxit=1000)
+            el += time.perf_counter() - t0
+            useful += mm.nt * so.iters
+        rate = useful / el
+        rows["batched"] = {"value": round(rate, 1), "unit": "tet CG iterations/s",
+                           "sample": f"{len(sel)} of the {len(meshes)} meshes (every 16th), one step each, serial, "
+                                     f"{el:.1f} s; the whole batch would take about "
+                                     f"{el * len(meshes) / len(sel):.0f} s (extrapolated by mesh count)",
+                           "gpu_over_oracle": round(extra["batched"]["tet_cg_iters_per_s"] / rate, 1)}
+    cpu["rows"] = rows
+    return cpu
 
 
 def main():
@@ -539,6 +684,9 @@ def main():
         pass
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "traffic_source": (f"not measured in this run: FETCH_SIZE + WRITE_SIZE counters from "
+                                   f"{os.path.relpath(TRAFFIC_FILE, ROOT)} for kernel sources {kernel_source_hash()}"
+                                   if traffic is not None else None),
                 "kernel": "stiffness-product call (block kernel + halo pass), cold, mean over the timed calls",
                 "algorithmic_bytes": bk, "mean_us": round(1e3 * tk_ms, 2)}
 
@@ -566,6 +714,7 @@ def main():
 
         t_step, s = time_step(0.0, 0.0)
         plain_rate = nt * s.iters / (t_step * 1e-3)
+        plain_step_rate = nt / (t_step * 1e-3)
         # per CG iteration: the K p element map (same bytes as a K u call) plus the vector
         # kernels (q = A p: y, p, mass, pinned in, q out; update: x, p, r, q, diag in, x, r, z
         # out; p = z + beta p: z, p in, p out)
@@ -582,7 +731,7 @@ def main():
                                             "cg_iters": sd.iters, "rel_res": sd.rel_res, "status": sd.status}
         log(f"implicit step {t_step:.3f} ms, damped {t_damp:.3f} ms")
     else:
-        plain_rate = None
+        plain_rate = plain_step_rate = None
     if not args.no_assembled:
         # the stiffness assembled on the edges relation (Vega's representation): one-time edge
         # build, assembly of K(d), and the block-CSR product against the matrix-free K u call
@@ -634,63 +783,12 @@ def main():
         extra["batched"] = bench_batch(stream, plain_rate)
         log(f"batched step {extra['batched']['step_ms']} ms")
     if not args.no_adjoint:
-        extra["adjoint"] = bench_adjoint(stream, plain_rate)
+        extra["adjoint"] = bench_adjoint(stream, plain_step_rate)
         log(f"adjoint fwd {extra['adjoint']['forward_ms']} ms bwd {extra['adjoint']['backward_ms']} ms")
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        ref = oracle.FEM.create(w.model, m.X, m.tets, w.E, w.nu, pinned=m.pinned)
-        dh = mg.perturbed_state(m, 0.02, seed=10)
-        uh = mg.direction(m, 11)
-        reps = 0
-        t0 = time.perf_counter()
-        while True:
-            ref.forces(dh)
-            ref.kmul(dh, uh)
-            reps += 1
-            if time.perf_counter() - t0 >= args.cpu_seconds:
-                break
-        el = time.perf_counter() - t0
-        cpu = {"value": round(reps * nt / el, 1), "unit": "tet force+Kmul evals/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{reps} force+Kmul passes over the full {nt}-tet mesh (FP64, serial C "
-                         f"oracle, 1 thread) in {el:.1f} s"}
-        # the oracle beside the other rows, on small bounded samples of the same workloads
-        rows = {}
-        t0 = time.perf_counter()
-        _d1, _v1, _dv, so = ref.implicit_step(dh, np.zeros_like(dh), w.dt, tol=0.0, maxit=5)
-        el = time.perf_counter() - t0
-        rows["implicit_step"] = {"value": round(nt * so.iters / el, 1), "unit": "tet CG iterations/s",
-                                 "sample": f"one step, 5 CG iterations, full mesh, {el:.2f} s (includes the "
-                                           f"force, K v and diagonal passes)"}
-        if "implicit_step" in extra:
-            rows["implicit_step"]["gpu_over_oracle"] = round(
-                extra["implicit_step"]["tet_cg_iters_per_s"] / rows["implicit_step"]["value"], 1)
-        if "assembled" in extra:
-            rp, col = oracle.edges(m.nv, m.tets)
-            blocks = ref.assemble(dh, rp, col)
-            t0 = time.perf_counter()
-            for _ in range(5):
-                oracle.spmv(rp, col, blocks, uh)
-            el = time.perf_counter() - t0
-            rows["assembled_spmv"] = {"value": round(5 * nt / el, 1), "unit": "tet-equivalent products/s",
-                                      "sample": f"5 block-CSR products, full mesh, {el:.2f} s"}
-            rows["assembled_spmv"]["gpu_over_oracle"] = round(
-                (nt / (extra["assembled"]["spmv_us"] * 1e-6)) / rows["assembled_spmv"]["value"], 1)
-        if "springs" in extra:
-            sw = mg.workload_springs(64)
-            sref = oracle.Springs(sw.mesh.X, sw.tail, sw.head, sw.mass, sw.K)
-            q1, qd1 = sw.q0, sw.qd0
-            t0 = time.perf_counter()
-            for _ in range(5):
-                q1, qd1 = sref.step(q1, qd1, sw.dt)
-            el = time.perf_counter() - t0
-            rows["springs"] = {"value": round(5 * len(sw.tail) / el, 1), "unit": "spring evals/s",
-                               "sample": f"5 steps, full 64^3 edge set, {el:.2f} s"}
-            rows["springs"]["gpu_over_oracle"] = round(extra["springs"]["edge_evals_per_s"] /
-                                                       rows["springs"]["value"], 1)
-        cpu["rows"] = rows
+        cpu = cpu_baseline(args, w, m, nt, extra)
 
     out = {
         "metric": "tet force+Kmul evals/s (1.6M tets); batched & adjoint vs plain, same GPU",

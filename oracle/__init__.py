@@ -77,11 +77,13 @@ def _load():
     lib.orc_kinetic_energy.argtypes = [I64, P, P]
     lib.orc_kinetic_energy.restype = D
     lib.orc_morton.argtypes = [I64, I64, P, P, P, P, P]
+    lib.orc_forces_mt.argtypes = base + [P, P, P, P, P, C.c_int]
+    lib.orc_kmul_mt.argtypes = base + [P, P, P, P, P, P, C.c_int]
     for f in ("orc_precompute", "orc_stress", "orc_dstress", "orc_d2stress",
               "orc_energy_density", "orc_forces", "orc_kmul", "orc_tmul", "orc_energy",
               "orc_jacobi_diag", "orc_implicit_step", "orc_step_vjp", "orc_group_by",
               "orc_morton", "orc_edges", "orc_assemble", "orc_spmv", "orc_spring_rest",
-              "orc_spring_forces", "orc_spring_apply"):
+              "orc_spring_forces", "orc_spring_apply", "orc_forces_mt", "orc_kmul_mt"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
     return lib
@@ -276,6 +278,31 @@ class FEM:
         u = _f64(u, (self.nv, 3))
         y = np.zeros((self.nv, 3))
         _chk(_load().orc_kmul(*self._base(), _p(d), _p(u), _p(y)), "kmul")
+        return y
+
+    def _mt_buffers(self):
+        if getattr(self, "_grp", None) is None:
+            self._grp = group_by(self.nv, self.tets)
+            self._part = np.zeros((max(self.nt, 1), 12))
+        return self._grp[0], self._grp[1], self._part
+
+    def forces_mt(self, d, threads):
+        """orc_forces on `threads` OpenMP threads (timing; equal bit for bit to forces)."""
+        d = _f64(d, (self.nv, 3))
+        f = np.zeros((self.nv, 3))
+        rp, inc, part = self._mt_buffers()
+        _chk(_load().orc_forces_mt(*self._base(), _p(d), _p(f), _p(rp), _p(inc), _p(part), int(threads)),
+             "forces_mt")
+        return f
+
+    def kmul_mt(self, d, u, threads):
+        """orc_kmul on `threads` OpenMP threads (timing; equal bit for bit to kmul)."""
+        d = _f64(d, (self.nv, 3))
+        u = _f64(u, (self.nv, 3))
+        y = np.zeros((self.nv, 3))
+        rp, inc, part = self._mt_buffers()
+        _chk(_load().orc_kmul_mt(*self._base(), _p(d), _p(u), _p(y), _p(rp), _p(inc), _p(part), int(threads)),
+             "kmul_mt")
         return y
 
     def assemble(self, d, row_ptr, col):

@@ -16,7 +16,8 @@ def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "ebb_oracle.c")
     # -ffp-contract=off: no fused multiply-add, so every product and sum is
     # rounded as written (the Morton quantisation relies on it).
-    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off",
+    # -fopenmp: only the *_mt timing entries use threads.
+    cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fopenmp",
            "-Wall", "-Wextra", "-o", LIB + ".tmp", src, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)

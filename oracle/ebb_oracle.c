@@ -336,6 +336,92 @@ int orc_kmul(int model, int64_t nv, int64_t nt, const int32_t *tets,
     return ORC_OK;
 }
 
+/* ---- multi-threaded forms, for timing the CPU baseline ----------------------------------
+ *
+ * The same element quantities with the tets split over threads: each tet writes its twelve
+ * corner values to its own row of part (nt x 12, corner-major), then each vertex sums its rows
+ * over the grouping (row_ptr, inc from orc_group_by), whose rows list a vertex's incidences in
+ * (tet, corner) order.  A vertex therefore receives the same terms in the same order as in the
+ * serial loop above, starting from zero, so the results are equal bit for bit. */
+
+/* the twelve corner values h[3c + r] that tet_scatter adds into out */
+static void tet_corners(double V0, const double P[9], const double *B, double h[12]) {
+    double Bt[9], H[9];
+    m_transpose(B, Bt);
+    m_mul(P, Bt, H);
+    for (int i = 0; i < 9; ++i) H[i] *= -V0;
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int c = 0; c < 3; ++c) {
+            h[3 * (c + 1) + r] = H[3 * r + c];
+            s += H[3 * r + c];
+        }
+        h[r] = -s;
+    }
+}
+
+static void gather_corners(int64_t nv, const int64_t *row_ptr, const int32_t *inc, const double *part,
+                           double *out, int nthreads) {
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t v = 0; v < nv; ++v) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+        for (int64_t j = row_ptr[v]; j < row_ptr[v + 1]; ++j) {
+            const double *h = part + 12 * (int64_t)(inc[j] >> 2) + 3 * (inc[j] & 3);
+            a0 += h[0];
+            a1 += h[1];
+            a2 += h[2];
+        }
+        out[3 * v] = a0;
+        out[3 * v + 1] = a1;
+        out[3 * v + 2] = a2;
+    }
+}
+
+int orc_forces_mt(int model, int64_t nv, int64_t nt, const int32_t *tets,
+                  const double *B, const double *V0, const double *mu, const double *lam,
+                  const double *d, double *f, const int64_t *row_ptr, const int32_t *inc, double *part,
+                  int nthreads) {
+    int err = ORC_OK;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t t = 0; t < nt; ++t) {
+        double G[9], P[9];
+        tet_grad(tets + 4 * t, d, B + 9 * t, G);
+        const int st = orc_stress(model, mu[t], lam[t], G, P);
+        if (st) {
+#pragma omp atomic write
+            err = st;
+            continue;
+        }
+        tet_corners(V0[t], P, B + 9 * t, part + 12 * t);
+    }
+    if (err) return err;
+    gather_corners(nv, row_ptr, inc, part, f, nthreads);
+    return ORC_OK;
+}
+
+int orc_kmul_mt(int model, int64_t nv, int64_t nt, const int32_t *tets,
+                const double *B, const double *V0, const double *mu, const double *lam,
+                const double *d, const double *u, double *y, const int64_t *row_ptr, const int32_t *inc,
+                double *part, int nthreads) {
+    int err = ORC_OK;
+#pragma omp parallel for num_threads(nthreads) schedule(static)
+    for (int64_t t = 0; t < nt; ++t) {
+        double G[9], dF[9], dP[9];
+        tet_grad(tets + 4 * t, d, B + 9 * t, G);
+        tet_grad(tets + 4 * t, u, B + 9 * t, dF);
+        const int st = orc_dstress(model, mu[t], lam[t], G, dF, dP);
+        if (st) {
+#pragma omp atomic write
+            err = st;
+            continue;
+        }
+        tet_corners(V0[t], dP, B + 9 * t, part + 12 * t);
+    }
+    if (err) return err;
+    gather_corners(nv, row_ptr, inc, part, y, nthreads);
+    return ORC_OK;
+}
+
 int orc_tmul(int model, int64_t nv, int64_t nt, const int32_t *tets,
              const double *B, const double *V0, const double *mu, const double *lam,
              const double *d, const double *a, const double *w, double *out) {

@@ -118,6 +118,18 @@ double orc_kinetic_energy(int64_t nv, const double *mass, const double *qd);
 /* Grouping of the tets.v[4] key-field by vertex: CSR of incidence 4t+c,
  * rows in (t, c) order.  row_ptr: nv+1, inc: 4 nt. */
 int orc_group_by(int64_t nv, int64_t nt, const int32_t *tets, int64_t *row_ptr, int32_t *inc);
+/* Multi-threaded orc_forces / orc_kmul for timing (OpenMP, nthreads threads): per-corner
+ * partials in part (nt x 12, caller-owned), then per-vertex sums over the grouping of
+ * orc_group_by in (tet, corner) order; equal bit for bit to the serial functions. */
+int orc_forces_mt(int model, int64_t nv, int64_t nt, const int32_t *tets,
+                  const double *B, const double *V0, const double *mu, const double *lam,
+                  const double *d, double *f, const int64_t *row_ptr, const int32_t *inc, double *part,
+                  int nthreads);
+int orc_kmul_mt(int model, int64_t nv, int64_t nt, const int32_t *tets,
+                const double *B, const double *V0, const double *mu, const double *lam,
+                const double *d, const double *u, double *y, const int64_t *row_ptr, const int32_t *inc,
+                double *part, int nthreads);
+
 
 /* Morton order of the rest positions.  codes[nv]; vperm[new] = old vertex;
  * tperm[new] = old tet (tets sorted by the min new vertex id of their

@@ -877,3 +877,22 @@ def test_morton_brute_force():
     c2, _, _ = oracle.morton(Xf, s.tets)
     mask = sum(1 << (3 * b + 2) for b in range(21))
     assert np.all((c2.astype(object) & mask) == 0)
+
+
+# --------------------------------------------------------------------------
+# multi-threaded timing entries of the oracle
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("model", MODELS)
+def test_threaded_forces_and_kmul_equal_the_serial_loop(model):
+    # per-corner partials summed over the grouping in (tet, corner) order give every vertex the
+    # serial loop's terms in its order: equal bit for bit, for any thread count
+    m, _, _ = mg.scramble(mg.jitter(mg.kuhn_cube(6), 0.02, seed=3), seed=5)
+    fem = oracle.FEM.create(model, m.X, m.tets, 1e5, 0.3)
+    rng = _rng(77)
+    d = 0.01 * rng.standard_normal((m.nv, 3)) / 6
+    u = rng.standard_normal((m.nv, 3))
+    f, y = fem.forces(d), fem.kmul(d, u)
+    for threads in (1, 3, 8):
+        assert np.array_equal(fem.forces_mt(d, threads), f)
+        assert np.array_equal(fem.kmul_mt(d, u, threads), y)
