@@ -187,15 +187,22 @@ enum { EBBX_STVK = 0, EBBX_NH = 1 };
  *              deterministic.  Needs at most 256 vertices per 256-tet block
  *              (a Morton-ordered mesh) and at most 1023 per super-block
  *              (EBBX_E_STATE / EBBX_E_ARG otherwise);
+ *   LANES:     as BLOCK (blocks of 64, 128 or 256 tets), but the stiffness
+ *              product spends four lanes on each tet: lane r of a quad owns
+ *              row (spatial component) r of every 3x3 quantity and the sums
+ *              over rows are reduced across the quad (DPP), trading issue
+ *              for registers per lane; the other element maps run as
+ *              BLOCK.  Bitwise deterministic;
  *   AUTO:      BLOCK with 256 tets per block (ebbx_fem_autotune times the
  *              alternatives on the domain itself).
  * The `block` argument of the calls below is the workgroup size (threads) for
  * ATOMIC and SEG, the number of tets per block (64..1024, a power of two)
- * for BLOCK and BLOCK_LDS, the owned vertices per block (64, 128 or 256) for
- * OWNER and the 256-tet blocks per workgroup (1..16) for PIPE; 0 picks the
+ * for BLOCK and BLOCK_LDS (64..256 for LANES), the owned vertices per block
+ * (64, 128 or 256) for OWNER and the 256-tet blocks per workgroup (1..16) for
+ * PIPE; 0 picks the
  * default (PIPE: 6, which on a Morton-ordered Kuhn mesh is 256 cells). */
 enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3,
-       EBBX_STRAT_BLOCK_LDS = 4, EBBX_STRAT_OWNER = 5, EBBX_STRAT_PIPE = 6 };
+       EBBX_STRAT_BLOCK_LDS = 4, EBBX_STRAT_OWNER = 5, EBBX_STRAT_PIPE = 6, EBBX_STRAT_LANES = 7 };
 
 typedef struct {
     int32_t model;       /* EBBX_STVK or EBBX_NH */

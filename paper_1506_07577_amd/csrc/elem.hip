@@ -769,7 +769,15 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
         if (finish_halo) launch_halo(F, out, accumulate, skip, s);
         return;
     }
-    if (F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS) {
+    if (F->strategy == EBBX_STRAT_LANES && op == OP_KMUL) {
+        const size_t shmem = lanes_shmem(F);
+        if (shmem > lds_limit())
+            fail(EBBX_E_STATE, "the multi-lane product needs %zu bytes of LDS per block; use smaller blocks", shmem);
+        launch_lanes(F, a, s);
+        if (finish_halo) launch_halo(F, out, accumulate, skip, s);
+        return;
+    }
+    if (F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS || F->strategy == EBBX_STRAT_LANES) {
         const size_t shmem = block_shmem(F, op);
         if (shmem > lds_limit())
             fail(EBBX_E_STATE, "block strategy needs %zu bytes of LDS per block (%d vertices); reorder the mesh "
@@ -1073,7 +1081,7 @@ int64_t elem_precompute(ebbx_fem_s *F, const double *X, const double *E_tet, hip
 HaloView elem_halo_view(const ebbx_fem_s *F) {
     HaloView h{};
     const bool block = F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS ||
-                       F->strategy == EBBX_STRAT_PIPE;
+                       F->strategy == EBBX_STRAT_PIPE || F->strategy == EBBX_STRAT_LANES;
     if (!block || F->sh_n == 0 || F->nt == 0) return h;
     h.row = F->sh_row.as<int32_t>();
     h.tab = F->sh_tab.as<int4>();

@@ -118,6 +118,10 @@ void build_pipe(ebbx_fem_s *F, int32_t g, hipStream_t s);
 // Launch the PIPE element kernel (pipe.hip); the halo pass is launched by the caller.
 void launch_pipe(ebbx_fem_s *F, ElemOp op, const ElemArgs &a, hipStream_t s);
 size_t pipe_shmem(const ebbx_fem_s *F, ElemOp op);
+// The stiffness product of the LANES strategy (lanes.hip): four lanes per tet over the BLOCK
+// tables; the halo pass is launched by the caller.
+void launch_lanes(ebbx_fem_s *F, const ElemArgs &a, hipStream_t s);
+size_t lanes_shmem(const ebbx_fem_s *F);
 // Build the vertex-owned block tables of the OWNER strategy.
 void build_owner(ebbx_fem_s *F, int32_t verts_per_block, hipStream_t s);
 // Assembled stiffness on edges (assemble.hip): the edges relation (once per

@@ -52,7 +52,7 @@ const char *fem_relation_user(const ebbx_relation_s *r) {
 // `block`: threads per workgroup for ATOMIC and SEG (64..256, multiple of 64);
 // tets per block for BLOCK (64, 128, 256, 512 or 1024).  0 = default.
 void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s) {
-    if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_PIPE) fail(EBBX_E_ARG, "bad strategy %d", strategy);
+    if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_LANES) fail(EBBX_E_ARG, "bad strategy %d", strategy);
     // captured solver graphs hold pointers into the block, halo and owner tables that the
     // table builders below free and reallocate: drop them whenever the strategy is set
     step_drop_graphs(F);
@@ -81,9 +81,11 @@ void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s)
         F->block = g;
         return;
     }
-    if (strategy == EBBX_STRAT_BLOCK || strategy == EBBX_STRAT_BLOCK_LDS) {
+    if (strategy == EBBX_STRAT_BLOCK || strategy == EBBX_STRAT_BLOCK_LDS || strategy == EBBX_STRAT_LANES) {
         const int32_t bt = block ? block : 256;
         if (bt > 1024) fail(EBBX_E_ARG, "block strategies take at most 1024 tets per block");
+        if (strategy == EBBX_STRAT_LANES && bt > 256)
+            fail(EBBX_E_ARG, "the multi-lane product takes at most 256 tets per block (four lanes each)");
         if (!F->blocks_built || F->blk_tets != bt || F->halo_level != 0) build_blocks(F, bt, s);
         F->strategy = strategy;
         F->blk_red = strategy == EBBX_STRAT_BLOCK_LDS ? 1 : 0;

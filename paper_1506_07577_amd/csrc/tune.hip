@@ -33,6 +33,7 @@ const Candidate kCandidates[] = {
     {EBBX_STRAT_ATOMIC, 256},    {EBBX_STRAT_BLOCK, 64},      {EBBX_STRAT_OWNER, 64},
     {EBBX_STRAT_OWNER, 128},     {EBBX_STRAT_OWNER, 256},     {EBBX_STRAT_PIPE, 2},
     {EBBX_STRAT_PIPE, 4},        {EBBX_STRAT_PIPE, 6},        {EBBX_STRAT_PIPE, 8},
+    {EBBX_STRAT_LANES, 64},      {EBBX_STRAT_LANES, 128},     {EBBX_STRAT_LANES, 256},
 };
 
 uint64_t fnv1a(const void *p, size_t n, uint64_t h) {

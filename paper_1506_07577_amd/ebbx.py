@@ -23,7 +23,8 @@ E_DEGENERATE, E_INVERTED, E_NOT_SPD, E_NOT_CONVERGED, E_HIP, E_OOM, E_STATE, E_N
     -8, -9, -10, -11, -12, -13, -14, -15)
 F32, F64, I32, U8, I64 = 0, 1, 2, 3, 4
 STVK, NH = 0, 1
-STRAT_AUTO, STRAT_ATOMIC, STRAT_SEG, STRAT_BLOCK, STRAT_BLOCK_LDS, STRAT_OWNER, STRAT_PIPE = 0, 1, 2, 3, 4, 5, 6
+STRAT_AUTO, STRAT_ATOMIC, STRAT_SEG, STRAT_BLOCK, STRAT_BLOCK_LDS, STRAT_OWNER, STRAT_PIPE, STRAT_LANES = (
+    0, 1, 2, 3, 4, 5, 6, 7)
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 
 _DT = {torch.float32: F32, torch.float64: F64, torch.int32: I32, torch.uint8: U8, torch.int64: I64}

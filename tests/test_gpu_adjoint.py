@@ -40,7 +40,8 @@ def _gpu():
 
 def _strat(name):
     return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE}[name]
+            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE,
+            "lanes": ebbx.STRAT_LANES}[name]
 
 
 def _pair(m, model, E_tet, nu=0.3, prec="f64", strategy="block"):
@@ -67,7 +68,7 @@ MODELS = [("stvk", oracle.STVK), ("nh", oracle.NH)]
 # single evaluations
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("strategy", ["atomic", "seg", "block", "block_lds", "owner", "pipe"])
+@pytest.mark.parametrize("strategy", ["atomic", "seg", "block", "block_lds", "owner", "pipe", "lanes"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("mname,model", MODELS)
 def test_tmul_parity(mname, model, prec, strategy):

@@ -39,7 +39,8 @@ def _gpu():
 
 def _strat(name):
     return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE}[name]
+            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE,
+            "lanes": ebbx.STRAT_LANES}[name]
 
 
 def _pair(m, model, prec, strat, E=1e5, nu=0.3, E_tet=None, morton=False):
@@ -50,7 +51,7 @@ def _pair(m, model, prec, strat, E=1e5, nu=0.3, E_tet=None, morton=False):
     return mesh, ref
 
 
-@pytest.mark.parametrize("strat", ["atomic", "seg", "block", "owner", "pipe"])
+@pytest.mark.parametrize("strat", ["atomic", "seg", "block", "owner", "pipe", "lanes"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("model", [0, 1])
 def test_damped_step_parity(model, prec, strat):

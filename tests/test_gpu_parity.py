@@ -19,12 +19,13 @@ else:  # collected on a CPU host only to be deselected
     ebbx = None
 
 TOL = {"f64": 1e-10, "f32": 1e-5}
-STRATS = ["atomic", "seg", "block", "block_lds", "owner", "pipe"]
+STRATS = ["atomic", "seg", "block", "block_lds", "owner", "pipe", "lanes"]
 
 
 def _strat(name):
     return {"atomic": ebbx.STRAT_ATOMIC, "seg": ebbx.STRAT_SEG, "block": ebbx.STRAT_BLOCK,
-            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE}[name]
+            "block_lds": ebbx.STRAT_BLOCK_LDS, "owner": ebbx.STRAT_OWNER, "pipe": ebbx.STRAT_PIPE,
+            "lanes": ebbx.STRAT_LANES}[name]
 
 
 def _prec(p):
@@ -204,7 +205,7 @@ def test_morton_reordered_mesh_same_physics():
     mesh.fem.close()
 
 
-@pytest.mark.parametrize("strat", ["seg", "block", "owner", "pipe"])
+@pytest.mark.parametrize("strat", ["seg", "block", "owner", "pipe", "lanes"])
 def test_deterministic_strategies_bitwise_reproducible(strat):
     m = _mesh_small()
     mesh, _ = _pair(m, 1, "f32", strat, morton=True)
@@ -383,7 +384,7 @@ def test_locality_workload_full_size(order):
     seg_f, seg_k = mesh.fem.forces(dd).clone(), mesh.fem.kmul(dd, ud).clone()
     assert nerr(mesh.from_dev(seg_f), ef) <= 1e-10
     assert nerr(mesh.from_dev(seg_k), ek) <= 1e-10
-    for st in ["atomic", "block", "owner"] + (["pipe"] if order == "morton" else []):
+    for st in ["atomic", "block", "owner", "lanes"] + (["pipe"] if order == "morton" else []):
         mesh.fem.set_strategy(_strat(st), 64 if st == "owner" else 0)
         f, k = mesh.fem.forces(dd), mesh.fem.kmul(dd, ud)
         assert nerr(mesh.from_dev(f), ef) <= 1e-10, st
@@ -450,7 +451,8 @@ def test_randomized_small_meshes():
     precision, strategy and block size; forces, K u and the Jacobi diagonal against the oracle."""
     rng = np.random.default_rng(2024)
     blocks = {"atomic": [64, 128, 256], "seg": [64, 256], "block": [64, 128, 256, 512],
-              "block_lds": [64, 256], "owner": [64, 128], "pipe": [1, 2, 4, 8]}
+              "block_lds": [64, 256], "owner": [64, 128], "pipe": [1, 2, 4, 8],
+              "lanes": [64, 128, 256]}
     for case in range(12):
         n = int(rng.integers(1, 7))
         m = mg.jitter(mg.kuhn_cube(n), 0.01, seed=int(rng.integers(1 << 30)))
