@@ -274,6 +274,21 @@ ebbx_status ebbx_fem_forces(ebbx_fem fem, const double *d, double *f, int32_t ac
 ebbx_status ebbx_fem_Kmul(ebbx_fem fem, const double *d, const double *u, double *y,
                           int32_t accumulate, ebbx_stream stream);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): ebbx_fem_Kmul with
+ * the same arguments, kernels and results (bit for bit), except that the
+ * call's scratch -- the shared-vertex partials of the block strategies, the
+ * per-corner partials of SEG -- lives in a library-wide device array of
+ * EBBX_NOALLOC_SCRATCH_MIB MiB per GPU instead of buffers of the domain.  The
+ * call allocates nothing (the domain's tables are built when its strategy is
+ * set).  EBBX_E_ARG when the domain needs more scratch than the array holds.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams, other threads) race; calls in one stream are ordered.  The
+ * array keeps the last call's contents; a call writes every entry it reads. */
+#define EBBX_NOALLOC_SCRATCH_MIB 64
+ebbx_status ebbx_fem_Kmul_noalloc(ebbx_fem fem, const double *d, const double *u, double *y,
+                                  int32_t accumulate, ebbx_stream stream);
+
 /* Total strain energy W = sum V0 psi(F) into out_dev[0] (FP64):
  * StVK psi = mu E:E + lam tr(E)^2/2; NH psi = mu (tr(F^T F) - 3)/2 - mu ln J
  * + lam (ln J)^2/2. */

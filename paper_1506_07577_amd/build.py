@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libebbx.so")
-SOURCES = ["runtime.hip", "elem.hip", "pipe.hip", "lanes.hip", "fem.hip", "solve.hip", "tune.hip", "assemble.hip", "springs.hip"]
+SOURCES = ["runtime.hip", "elem.hip", "pipe.hip", "lanes.hip", "fem.hip", "solve.hip", "tune.hip", "assemble.hip", "springs.hip", "noalloc.hip"]
 ARCH = os.environ.get("EBBX_ARCH", "gfx950")
 
 CFLAGS = [

@@ -707,11 +707,10 @@ static size_t lds_limit() {
 }
 
 // Sum each shared vertex's halo entries into out (the second pass of the block strategies).
-static void launch_halo(ebbx_fem_s *F, double *out, int accumulate, const int *skip, hipStream_t s) {
+static void launch_halo(ebbx_fem_s *F, const double *hl, double *out, int accumulate, const int *skip, hipStream_t s) {
     if (F->sh_n <= 0) return;
     const int64_t nv = F->nv;
     const dim3 g(grid_n(F->sh_n, 256, 1ll << 20));
-    const double *hl = (const double *)F->halo.get();
     const int32_t *sv = F->sh_vert.as<int32_t>();
     const int4 *tb = F->sh_tab.as<int4>();
     const uint32_t sn = (uint32_t)F->sh_n;
@@ -728,7 +727,8 @@ static void launch_halo(ebbx_fem_s *F, double *out, int accumulate, const int *s
 }
 
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
-                 hipStream_t s, const int *skip, const double *w, const int *mdone, bool finish_halo) {
+                 hipStream_t s, const int *skip, const double *w, const int *mdone, bool finish_halo,
+                 void *scratch) {
     const int64_t nt = F->nt, nv = F->nv;
     if (nv == 0) return;
     if (nt == 0) {
@@ -741,6 +741,10 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
     set_vec(a.w, w, (uint32_t)nv);
     for (int k = 0; k < 3; ++k) a.out[k] = out + (size_t)k * nv;
     a.part = F->part.get();
+    if (scratch) {   // the caller's buffer replaces the domain's halo (block strategies) or partials (SEG)
+        a.halo = (double *)scratch;
+        a.part = scratch;
+    }
     a.skip = skip;
     a.mdone = F->tmesh ? mdone : nullptr;
     a.accumulate = accumulate;
@@ -766,7 +770,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
             fail(EBBX_E_STATE, "pipelined blocks need %zu bytes of LDS per workgroup; use fewer blocks per "
                  "workgroup", shmem);
         launch_pipe(F, op, a, s);
-        if (finish_halo) launch_halo(F, out, accumulate, skip, s);
+        if (finish_halo) launch_halo(F, a.halo, out, accumulate, skip, s);
         return;
     }
     if (F->strategy == EBBX_STRAT_LANES && op == OP_KMUL) {
@@ -774,7 +778,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
         if (shmem > lds_limit())
             fail(EBBX_E_STATE, "the multi-lane product needs %zu bytes of LDS per block; use smaller blocks", shmem);
         launch_lanes(F, a, s);
-        if (finish_halo) launch_halo(F, out, accumulate, skip, s);
+        if (finish_halo) launch_halo(F, a.halo, out, accumulate, skip, s);
         return;
     }
     if (F->strategy == EBBX_STRAT_BLOCK || F->strategy == EBBX_STRAT_BLOCK_LDS || F->strategy == EBBX_STRAT_LANES) {
@@ -792,7 +796,7 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
             if (F->model == EBBX_STVK) launch_model<double, EBBX_STVK>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
             else launch_model<double, EBBX_NH>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);
         }
-        if (finish_halo) launch_halo(F, out, accumulate, skip, s);
+        if (finish_halo) launch_halo(F, a.halo, out, accumulate, skip, s);
         return;
     }
     const int sc = F->strategy == EBBX_STRAT_SEG ? SC_PART : SC_ATOMIC;
@@ -808,12 +812,24 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
     if (sc == SC_PART) {
         const unsigned g = grid_n(nv, 256, 1ll << 31);
         if (F->prec == EBBX_F32)
-            hipLaunchKernelGGL(k_seg_gather<float>, dim3(g), dim3(256), 0, s, (const float *)F->part.get(),
+            hipLaunchKernelGGL(k_seg_gather<float>, dim3(g), dim3(256), 0, s, (const float *)a.part,
                                F->group->row_ptr.as<int64_t>(), F->group->inc.as<int32_t>(), nv, out, accumulate);
         else
-            hipLaunchKernelGGL(k_seg_gather<double>, dim3(g), dim3(256), 0, s, (const double *)F->part.get(),
+            hipLaunchKernelGGL(k_seg_gather<double>, dim3(g), dim3(256), 0, s, (const double *)a.part,
                                F->group->row_ptr.as<int64_t>(), F->group->inc.as<int32_t>(), nv, out, accumulate);
         HIPCHK(hipGetLastError());
+    }
+}
+
+size_t elem_scratch_bytes(const ebbx_fem_s *F, ElemOp op) {
+    if (F->nv == 0 || F->nt == 0) return 0;
+    switch (F->strategy) {
+    case EBBX_STRAT_SEG: return (size_t)F->nt * 12 * F->esize;
+    case EBBX_STRAT_BLOCK:
+    case EBBX_STRAT_BLOCK_LDS:
+    case EBBX_STRAT_LANES:
+    case EBBX_STRAT_PIPE: return (size_t)F->halo_n * 3 * sizeof(double);
+    default: (void)op; return 0;   // ATOMIC, OWNER: no scratch
     }
 }
 

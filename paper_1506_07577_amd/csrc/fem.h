@@ -62,10 +62,15 @@ struct ElemArgs {
 // out (3, nv) (+= if accumulate).  For OP_DIAG, u is ignored and out receives
 // the raw stiffness diagonal K[(v,c),(v,c)].
 // finish_halo = false (block strategies) leaves the shared vertices' sums in the
-// halo for a consumer that reads them through elem_halo_view.
+// halo for a consumer that reads them through elem_halo_view.  scratch (nullable): a
+// device buffer of at least elem_scratch_bytes(F, op) bytes used in place of the
+// domain's own halo (block strategies) or per-corner partials (SEG) for this call.
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
                  hipStream_t s, const int *skip = nullptr, const double *w = nullptr, const int *mdone = nullptr,
-                 bool finish_halo = true);
+                 bool finish_halo = true, void *scratch = nullptr);
+// Device scratch one element map of the current strategy writes and reads besides its
+// inputs, outputs and the domain's tables (0 for ATOMIC and OWNER).
+size_t elem_scratch_bytes(const ebbx_fem_s *F, ElemOp op);
 
 // The unfinished output of a block-strategy element map: vertex v's value is
 // out[v] when row[v] < 0, else the sum of its halo entries (row r of the

@@ -105,6 +105,7 @@ def lib():
         "ebbx_fem_get_strategy": ([P, C.POINTER(I32_), C.POINTER(I32_)], I32_),
         "ebbx_fem_forces": ([P, P, P, I32_, P], I32_),
         "ebbx_fem_Kmul": ([P, P, P, P, I32_, P], I32_),
+        "ebbx_fem_Kmul_noalloc": ([P, P, P, P, I32_, P], I32_),
         "ebbx_fem_energy": ([P, P, P, P], I32_),
         "ebbx_fem_jacobi_diag": ([P, P, D, P, P], I32_),
         "ebbx_fem_mass": ([P, P, P], I32_),
@@ -327,6 +328,15 @@ class Fem:
         self._vec(y, "y")
         _check(lib().ebbx_fem_Kmul(self.h, _ptr(d), _ptr(u), _ptr(y), int(bool(accumulate)),
                                    _stream(stream)))
+        return y
+
+    def kmul_noalloc(self, d, u, y, accumulate=False, stream=None):
+        """kmul through the allocation-free entry point: y must be given (nothing is allocated)."""
+        self._vec(d, "d")
+        self._vec(u, "u")
+        self._vec(y, "y")
+        _check(lib().ebbx_fem_Kmul_noalloc(self.h, _ptr(d), _ptr(u), _ptr(y), int(bool(accumulate)),
+                                           _stream(stream)))
         return y
 
     def assemble(self, d, stream=None):
