@@ -201,7 +201,8 @@ def bench_autotune(stream, n):
     torch.cuda.synchronize()
     tune_s = time.perf_counter() - t0
     names = {ebbx.STRAT_ATOMIC: "atomic", ebbx.STRAT_SEG: "seg", ebbx.STRAT_BLOCK: "block",
-             ebbx.STRAT_BLOCK_LDS: "block_lds", ebbx.STRAT_OWNER: "owner"}
+             ebbx.STRAT_BLOCK_LDS: "block_lds", ebbx.STRAT_OWNER: "owner", ebbx.STRAT_PIPE: "pipe",
+             ebbx.STRAT_LANES: "lanes"}
     chosen = mesh.fem.get_strategy()
     out = {"mesh": f"{n}^3 Morton", "tune_s": round(tune_s, 2),
            "chosen": {"strategy": names.get(chosen[0], chosen[0]), "block": chosen[1]},
