@@ -157,26 +157,19 @@ __device__ __forceinline__ void staged_grad(const double *s, uint32_t S, const u
     grad_from(q, b, G);
 }
 
+// One tet block (blk) of the BLOCK strategies, evaluated by the whole workgroup.
 template <class T, int MODEL, int OP, int TPT, int W, int RED>
-__global__ __launch_bounds__(512) void k_block(ElemArgs a) {
+__device__ __forceinline__ void block_body(const ElemArgs &a, uint32_t blk, uint32_t tid) {
     extern __shared__ uint4 s_dyn4[];
-    if (a.skip && *a.skip) return;   // uniform over the grid
     const uint32_t nt = a.nt;
-    const uint32_t tid = threadIdx.x, nthr = blockDim.x, BT = nthr * TPT;
+    const uint32_t nthr = blockDim.x, BT = nthr * TPT;
     const uint32_t LB = 4 * BT;   // rows of one component column of the per-corner results
-    const uint32_t blk = xcd_block(blockIdx.x, a.nblk, a.xcd_run_log2);
     // block tables at a fixed stride S (padded with vertex -1): no dependent offset load
     const uint32_t S = a.blk_stride;
     const int32_t *bverts = a.blk_verts + (size_t)blk * S;
     const int32_t *bhpos = a.blk_hpos + (size_t)blk * S;
     const uint16_t *brow = a.blk_row + (size_t)blk * (S + 1);
     const uint32_t t0 = blk * BT;
-    if (a.mdone) {   // a batch: skip the block once every mesh it touches has finished (uniform)
-        const int32_t m0 = a.tmesh[t0], m1 = a.tmesh[min(t0 + BT, nt) - 1];
-        bool all = true;
-        for (int32_t m = m0; m <= m1; ++m) all = all && a.mdone[m] != 0;
-        if (all) return;
-    }
     // RED == 0: per-corner result rows in the block's incidence order (deterministic sums);
     // RED == 1: FP64 LDS atomics into one accumulator per block vertex
     constexpr int NQ = OP == OP_TMUL ? 3 : OP == OP_KMUL ? 2 : 1;   // staged vertex fields
@@ -369,6 +362,64 @@ __global__ __launch_bounds__(512) void k_block(ElemArgs a) {
                 hq[2] = v2;
             }
         }
+    }
+}
+
+template <class T, int MODEL, int OP, int TPT, int W, int RED>
+__global__ __launch_bounds__(512) void k_block(ElemArgs a) {
+    if (a.skip && *a.skip) return;   // uniform over the grid
+    const uint32_t blk = xcd_block(blockIdx.x, a.nblk, a.xcd_run_log2);
+    if (a.mdone) {   // a batch: skip the block once every mesh it touches has finished (uniform)
+        const uint32_t BT = blockDim.x * TPT, t0 = blk * BT;
+        const int32_t m0 = a.tmesh[t0], m1 = a.tmesh[min(t0 + BT, a.nt) - 1];
+        bool all = true;
+        for (int32_t m = m0; m <= m1; ++m) all = all && a.mdone[m] != 0;
+        if (all) return;
+    }
+    block_body<T, MODEL, OP, TPT, W, RED>(a, blk, threadIdx.x);
+}
+
+// The block kernel of a batched solve over the list of the blocks of its unfinished meshes
+// (a.act; see ActList): a fixed grid of workgroups, each taking one contiguous stretch of the
+// list (XCD x's workgroups, x = workgroup mod 8, one contiguous eighth of it), so iterations in
+// which few meshes still iterate dispatch no workgroups for the finished ones.
+// The loop costs registers: the FP32 products would need 80-88 VGPRs (5 waves per SIMD)
+// against 55-69 for k_block; they are held to 6 waves (80 VGPRs, at most a couple spilled).
+template <class T, int MODEL, int OP, int W>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 1))) void k_block_list(ElemArgs a) {
+    __shared__ int32_t s_m[1];
+    if (a.skip && *a.skip) return;   // uniform over the grid
+    const ActList L = act_list(a.act, a.act_nm);
+    const uint32_t n = (uint32_t)L.hdr[0], G = gridDim.x;
+    const uint32_t r = (blockIdx.x & 7u) * (G >> 3) + (blockIdx.x >> 3);   // G is a multiple of 8
+    const uint32_t i0 = (uint32_t)(((uint64_t)r * n) / G), i1 = (uint32_t)(((uint64_t)(r + 1) * n) / G);
+    if (i0 >= i1) return;
+    // the list range holding item i0 (bpfx is ascending; ranges may be empty)
+    const int32_t nam = L.hdr[2];
+    if (threadIdx.x == 0) s_m[0] = 0;
+    __syncthreads();
+    for (int32_t j = threadIdx.x; j < nam; j += blockDim.x)
+        if ((uint32_t)L.bpfx[j] <= i0 && i0 < (uint32_t)L.bpfx[j + 1]) s_m[0] = j;
+    __syncthreads();
+    // list positions are the same in every lane: keep them in scalar registers, so that the
+    // block's table addresses stay scalar as in k_block
+    int32_t j = __builtin_amdgcn_readfirstlane(s_m[0]);
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane(L.bpfx[j]);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane(L.bpfx[j + 1]);
+    for (uint32_t i = i0; i < i1; ++i) {
+        while (i >= hi) {
+            ++j;
+            lo = hi;
+            hi = (uint32_t)__builtin_amdgcn_readfirstlane(L.bpfx[j + 1]);
+        }
+        if (i > i0) __syncthreads();   // the previous block is done with the LDS
+        const uint32_t blk = (uint32_t)__builtin_amdgcn_readfirstlane(L.bstart[j]) + (i - lo);
+        // the thread index passes through an empty asm statement, so that the compiler does not
+        // hoist the per-thread values the body derives from it out of the loop and keep them
+        // live across blocks (98 VGPRs against the body's 69 for the FP32 neo-Hookean product)
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        block_body<T, MODEL, OP, 1, W, 0>(a, blk, tid);
     }
 }
 
@@ -643,6 +694,28 @@ static void launch_model(bool block, ElemOp op, int sc, int tpt, int w, int red,
     }
 }
 
+bool elem_list_ok(const ebbx_fem_s *F, ElemOp op) {
+    return op == OP_KMUL && F->strategy == EBBX_STRAT_BLOCK && F->blk_red == 0 && F->blk_tets <= 512;
+}
+
+// The list-driven block kernel runs as many workgroups as fit on the device at once (a
+// multiple of 8, one share per XCD), so that each takes one stretch of the list.
+template <class T, int MODEL>
+static void launch_block_list(ebbx_fem_s *F, const ElemArgs &a, int threads, size_t shmem, hipStream_t s) {
+    auto run = [&](auto kern) {
+        int per_cu = 0, dev = 0, ncu = 0;
+        HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, shmem));
+        HIPCHK(hipGetDevice(&dev));
+        HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        const int64_t g = (int64_t)std::max(per_cu, 1) * std::max(ncu, 1);
+        const unsigned grid = (unsigned)std::max<int64_t>(8, std::min<int64_t>(g, ((int64_t)F->nblk + 7) / 8 * 8) / 8 * 8);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(threads), shmem, s, a);
+        HIPCHK(hipGetLastError());
+    };
+    if (F->blk_w == 1) run(k_block_list<T, MODEL, OP_KMUL, 1>);
+    else run(k_block_list<T, MODEL, OP_KMUL, 2>);
+}
+
 static ElemArgs base_args(ebbx_fem_s *F) {
     ElemArgs a{};
     const uint32_t nt = (uint32_t)F->nt, nv = (uint32_t)F->nv;
@@ -728,7 +801,7 @@ static void launch_halo(ebbx_fem_s *F, const double *hl, double *out, int accumu
 
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
                  hipStream_t s, const int *skip, const double *w, const int *mdone, bool finish_halo,
-                 void *scratch) {
+                 void *scratch, const int32_t *act) {
     const int64_t nt = F->nt, nv = F->nv;
     if (nv == 0) return;
     if (nt == 0) {
@@ -747,6 +820,8 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
     }
     a.skip = skip;
     a.mdone = F->tmesh ? mdone : nullptr;
+    a.act = F->tmesh ? act : nullptr;
+    a.act_nm = (int32_t)F->nm;
     a.accumulate = accumulate;
     if (F->strategy == EBBX_STRAT_OWNER) {
         const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
@@ -788,6 +863,17 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
                  "(Morton) or use smaller blocks", shmem, F->blk_maxv);
         const int threads = std::min(F->blk_tets, 512), tpt = F->blk_tets / threads;
         if (tpt > 2) fail(EBBX_E_ARG, "block strategy: at most 1024 tets per block");
+        if (a.act && elem_list_ok(F, op)) {
+            if (F->prec == EBBX_F32) {
+                if (F->model == EBBX_STVK) launch_block_list<float, EBBX_STVK>(F, a, threads, shmem, s);
+                else launch_block_list<float, EBBX_NH>(F, a, threads, shmem, s);
+            } else {
+                if (F->model == EBBX_STVK) launch_block_list<double, EBBX_STVK>(F, a, threads, shmem, s);
+                else launch_block_list<double, EBBX_NH>(F, a, threads, shmem, s);
+            }
+            if (finish_halo) launch_halo(F, a.halo, out, accumulate, skip, s);
+            return;
+        }
         const unsigned grid = (unsigned)F->nblk;
         if (F->prec == EBBX_F32) {
             if (F->model == EBBX_STVK) launch_model<float, EBBX_STVK>(true, op, 0, tpt, F->blk_w, F->blk_red, a, threads, grid, shmem, s);

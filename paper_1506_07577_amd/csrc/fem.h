@@ -9,6 +9,19 @@ namespace ebbx {
 
 enum ElemOp { OP_FORCE = 0, OP_KMUL = 1, OP_DIAG = 2, OP_TMUL = 3 };
 
+// The tet blocks of a batched solve still to evaluate, rebuilt from the meshes' finished flags
+// at the start of every CG iteration: one range per unfinished mesh, in mesh order.  hdr[0] is
+// the number of blocks, hdr[2] the number of unfinished meshes; range j covers list items
+// [bpfx[j], bpfx[j+1]), the blocks bstart[j] + (i - bpfx[j]).  A block that two unfinished
+// meshes share is listed once, in the first one's range.  Laid out as int32 [4 | nm + 1 | nm].
+struct ActList {
+    const int32_t *hdr, *bpfx, *bstart;
+};
+__host__ __device__ inline ActList act_list(const int32_t *p, int32_t nm) {
+    return ActList{p, p + 4, p + 4 + (nm + 1)};
+}
+inline size_t act_list_ints(int64_t nm) { return (size_t)(4 + (nm + 1) + nm); }
+
 // Everything an element kernel reads; plain pointers, passed by value.  Column
 // stores are passed as one base pointer per component, so that a kernel
 // addresses every column of a row with one 32-bit byte offset.
@@ -56,6 +69,8 @@ struct ElemArgs {
     const int *skip;            // nullable device flag: nonzero = return at once (converged solve)
     const int *mdone;           // nullable per-mesh finished flags (batch): a block whose meshes are
                                 // all finished returns at once (block strategies)
+    const int32_t *act;         // nullable: the active list of a batched solve (k_block_list)
+    int32_t act_nm;             // meshes of that batch (the list's array stride)
 };
 
 // Launch the element map `op` with the FEM's current strategy; result into
@@ -67,7 +82,10 @@ struct ElemArgs {
 // domain's own halo (block strategies) or per-corner partials (SEG) for this call.
 void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, double *out, int accumulate,
                  hipStream_t s, const int *skip = nullptr, const double *w = nullptr, const int *mdone = nullptr,
-                 bool finish_halo = true, void *scratch = nullptr);
+                 bool finish_halo = true, void *scratch = nullptr, const int32_t *act = nullptr);
+// Whether the element map `op` of F's strategy can run over an active list (act of
+// elem_launch, batches only): the stiffness product of the BLOCK strategy, one tet per thread.
+bool elem_list_ok(const ebbx_fem_s *F, ElemOp op);
 // Device scratch one element map of the current strategy writes and reads besides its
 // inputs, outputs and the domain's tables (0 for ATOMIC and OWNER).
 size_t elem_scratch_bytes(const ebbx_fem_s *F, ElemOp op);
@@ -170,6 +188,7 @@ struct ebbx_fem_s {
     // meshes of a batch: vertex ranges [mesh_vptr[m], mesh_vptr[m+1]); one mesh otherwise
     int64_t nm = 1;
     std::vector<int64_t> mesh_vptr;
+    std::vector<int64_t> mesh_tptr;   // batches: tet ranges [mesh_tptr[m], mesh_tptr[m+1])
     const int32_t *tmesh = nullptr;  // per-tet mesh ids (batch) or NULL
     bool batch_owned = false;        // the union domain of a batch: destroyed with it
     size_t esize = 8;   // bytes of one element-precision value

@@ -149,6 +149,62 @@ __device__ __forceinline__ void mark_done(CGState &st, SolveCtl *ctl, int m) {
     if (atomicSub(&ctl->n_active, 1) == 1) ctl->all_done = 1;
 }
 
+// Rebuild the active list (ActList) of a batched solve from the meshes' finished flags, at the
+// start of a CG iteration; one workgroup.  Mesh m's tets are [tptr[m], tptr[m+1]), its blocks
+// of bt tets those holding them; a block it shares with an earlier unfinished mesh is that
+// mesh's.  Scans are in mesh order, so the list is the same on every run.
+__global__ __launch_bounds__(VT) void k_active(const SolveCtl *ctl, const int64_t *tptr, const int32_t *tmesh,
+                                               int32_t nm, int32_t bt, int32_t *act) {
+    __shared__ int32_t s_x[2][VT];
+    const int *done = (const int *)(ctl + 1);
+    int32_t *hdr = act, *bpfx = act + 4, *bstart = bpfx + (nm + 1);
+    int32_t cn = 0, cb = 0;   // carried over the tiles: meshes, blocks
+    const int tid = threadIdx.x;
+    for (int32_t base = 0; base < nm; base += VT) {
+        const int32_t m = base + tid;
+        const bool on = m < nm && !done[m];
+        int32_t nb = 0, bs = 0;
+        if (on) {
+            const int64_t t0 = tptr[m], t1 = tptr[m + 1];
+            if (t1 > t0) {
+                const int64_t b0 = t0 / bt, b1 = (t1 - 1) / bt + 1;
+                const bool taken = t0 > 0 && (t0 - 1) / bt == b0 && !done[tmesh[t0 - 1]];
+                bs = (int32_t)(b0 + (taken ? 1 : 0));
+                nb = (int32_t)(b1 - bs);
+            }
+        }
+        // inclusive scans of (on, nb) over the tile (Hillis-Steele in LDS)
+        int32_t v0 = on ? 1 : 0, v1 = nb;
+        s_x[0][tid] = v0;
+        s_x[1][tid] = v1;
+        __syncthreads();
+        for (int o = 1; o < VT; o <<= 1) {
+            const int32_t a0 = tid >= o ? s_x[0][tid - o] : 0, a1 = tid >= o ? s_x[1][tid - o] : 0;
+            __syncthreads();
+            v0 += a0;
+            v1 += a1;
+            s_x[0][tid] = v0;
+            s_x[1][tid] = v1;
+            __syncthreads();
+        }
+        if (on) {
+            const int32_t k = cn + v0 - 1;
+            bpfx[k] = cb + v1 - nb;
+            bstart[k] = bs;
+        }
+        cn += s_x[0][VT - 1];
+        cb += s_x[1][VT - 1];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        bpfx[cn] = cb;
+        hdr[0] = cb;
+        hdr[1] = 0;
+        hdr[2] = cn;
+        hdr[3] = 0;
+    }
+}
+
 struct StepVec {
     double *dn, *vn, *f, *y, *r, *z, *p, *q, *x, *diag;
 };
@@ -584,6 +640,7 @@ using namespace ebbx;
 
 struct ebbx_fem_s::Step {
     DevBuf vec, part, state, ctl, chunks;
+    DevBuf act, tptr;   // batches: the active list and the meshes' tet offsets (nm + 1)
     StepVec w{};
     Chunks ch{};
     int nch = 0, nm = 1;
@@ -648,6 +705,8 @@ struct SolveBufs {
     double *part;
     int nch, nm;
     bool fused;
+    int32_t *act;           // batches: the active list (NULL: every kernel covers every mesh)
+    const int64_t *tptr;    // batches: the meshes' tet offsets
 };
 
 // The preamble of `mode` (0: step, 1: adjoint solve) onto stream cs: state reset, (step)
@@ -680,9 +739,17 @@ void launch_iterations(ebbx_fem_s *F, const ebbx_step_params &p, const SolveBufs
     CGState *st = b.st;
     SolveCtl *ctl = b.ctl;
     double *part = b.part;
+    // a batch in the block strategy evaluates K p over a list of the blocks of its unfinished
+    // meshes, rebuilt at the start of every iteration, so finished meshes cost no workgroups
+    const bool list = b.act && elem_list_ok(F, OP_KMUL);
+    const int32_t *act = list ? b.act : nullptr;
     for (int it = 0; it < count && it < p.maxit; ++it) {
+        if (list) {
+            hipLaunchKernelGGL(k_active, dim3(1), dim3(VT), 0, cs, (const SolveCtl *)ctl, b.tptr, F->tmesh,
+                               (int32_t)b.nm, (int32_t)F->blk_tets, b.act);
+        }
         elem_launch(F, OP_KMUL, b.w.dn, b.w.p, b.w.y, 0, cs, &ctl->all_done, nullptr,
-                    b.nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr);
+                    b.nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr, nullptr, act);
         hipLaunchKernelGGL(k_cg_Ap, dim3(b.nch), dim3(VT), 0, cs, b.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
                            nv, cm, ck, (const CGState *)st, b.ch, hv, part);
         if (b.fused) {
@@ -704,7 +771,8 @@ void launch_iterations(ebbx_fem_s *F, const ebbx_step_params &p, const SolveBufs
 SolveBufs step_bufs(ebbx_fem_s *F) {
     auto &S = *F->step;
     return SolveBufs{S.w, S.ch, S.state.as<CGState>(), S.ctl.as<SolveCtl>(), S.part.as<double>(), S.nch, S.nm,
-                     S.fused};
+                     S.fused, S.nm > 1 ? S.act.as<int32_t>() : nullptr,
+                     S.nm > 1 ? S.tptr.as<int64_t>() : nullptr};
 }
 
 // Capture the preamble of `mode` (0: step, 1: adjoint solve) and, if the
@@ -805,6 +873,12 @@ void ensure_step(ebbx_fem_s *F, hipStream_t s) {
     int32_t most = 0;
     for (int64_t m = 0; m < nm; ++m) most = std::max(most, cptr[(size_t)m + 1] - cptr[(size_t)m]);
     S->fused = most <= FUSE_CHUNKS;
+    if (nm > 1) {
+        if ((int64_t)F->mesh_tptr.size() != nm + 1) fail(EBBX_E_STATE, "batch without per-mesh tet offsets");
+        S->act.reset(act_list_ints(nm) * sizeof(int32_t), s);
+        S->tptr.reset((size_t)(nm + 1) * sizeof(int64_t), s);
+        HIPCHK(hipMemcpyAsync(S->tptr.get(), F->mesh_tptr.data(), (nm + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    }
     S->state.reset((size_t)std::max<int64_t>(nm, 1) * sizeof(CGState), s);
     S->ctl.reset(sizeof(SolveCtl) + (size_t)std::max<int64_t>(nm, 1) * sizeof(int), s);
     HIPCHK(hipStreamCreateWithFlags(&S->cap, hipStreamNonBlocking));
@@ -1011,6 +1085,11 @@ ebbx_status ebbx_batch_create(ebbx_relation meshes, ebbx_relation tets, ebbx_rel
     auto grp = build_group(vr, fields->vert_mesh, s);
     F->mesh_vptr.assign((size_t)nm + 1, 0);
     HIPCHK(hipMemcpyAsync(F->mesh_vptr.data(), grp->row_ptr.get(), (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
+                          s));
+    // tet ranges of the meshes (the tets are sorted by mesh, checked above)
+    auto tgrp = build_group(tr, fields->tet_mesh, s);
+    F->mesh_tptr.assign((size_t)nm + 1, 0);
+    HIPCHK(hipMemcpyAsync(F->mesh_tptr.data(), tgrp->row_ptr.get(), (nm + 1) * sizeof(int64_t), hipMemcpyDeviceToHost,
                           s));
     F->nm = nm;
     F->tmesh = tk.ptr;

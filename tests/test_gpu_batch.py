@@ -196,7 +196,8 @@ def test_batch_errors():
 
 def test_batch_full_size_sampled():
     """256 cubes with sides 8..40 (about 31M tets), neo-Hookean, FP32 elements, per-mesh E and nu,
-    CG to 1e-8: every mesh converges; the smallest, a median and the largest mesh match the oracle."""
+    CG to 1e-8: every mesh converges; every 8th mesh of the batch (32 meshes), the smallest, a
+    median and the largest mesh match the oracle."""
     meshes, E, nu = mg.workload_batch()
     un = mg.union(meshes)
     bm = ebbx.BatchMesh(un, E, nu, model=ebbx.NH, elem_prec=ebbx.F32)
@@ -207,12 +208,13 @@ def test_batch_full_size_sampled():
     assert max(s.rel_res for s in st) <= 1e-8
     sizes = np.array([m.nt for m in meshes])
     order = np.argsort(sizes, kind="stable")
-    pick = [int(order[0]), int(order[len(order) // 2]), int(order[-1])]
+    pick = sorted(set(range(0, len(meshes), 8)) | {int(order[0]), int(order[len(order) // 2]), int(order[-1])})
+    assert len(pick) >= 32
     gv = bm.from_dev(vv)
     for i in pick:
         m = meshes[i]
         a, b = un.vptr[i], un.vptr[i + 1]
         ref = oracle.FEM.create(ebbx.NH, m.X, m.tets, E[i], nu[i], pinned=m.pinned)
         z = np.zeros((m.nv, 3))
-        _d1, v1, _dv, _s = ref.implicit_step(z, z, 1e-3, tol=1e-8, maxit=1000)
+        _d1, v1, _dv, _so = ref.implicit_step(z, z, 1e-3, tol=1e-8, maxit=1000)
         assert nerr(gv[a:b], v1) < 1e-5, i
