@@ -182,6 +182,12 @@ def bench_small(stream):
             "note": "warm calls, HIP events per call (launch latency included); no roofline at this size"}
 
 
+def cand_name(names, sid, blk):
+    """strategy/block, with "x2" for two tets per thread"""
+    two = blk & 0x10000
+    return f"{names.get(sid, sid)}/{blk & 0xffff}" + ("x2" if two else "")
+
+
 def bench_autotune(stream, n):
     """The autotuner on the headline mesh (64^3 neo-Hookean FP32, Morton order): every strategy
     and block size timed on the stiffness product, the fastest kept; no cache."""
@@ -205,8 +211,8 @@ def bench_autotune(stream, n):
              ebbx.STRAT_LANES: "lanes"}
     chosen = mesh.fem.get_strategy()
     out = {"mesh": f"{n}^3 Morton", "tune_s": round(tune_s, 2),
-           "chosen": {"strategy": names.get(chosen[0], chosen[0]), "block": chosen[1]},
-           "candidates_us": {f"{names.get(sid, sid)}/{blk}": round(us, 2) for sid, blk, us in res},
+           "chosen": cand_name(names, chosen[0], chosen[1]),
+           "candidates_us": {cand_name(names, sid, blk): round(us, 2) for sid, blk, us in res},
            "note": "stiffness product, warm calls timed by the tuner (5 after 2 warm-up, HIP events)"}
     mesh.fem.close()
     return out
@@ -226,6 +232,9 @@ def bench_batch(stream, plain_rate):
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     log(f"batch: {bm.nm} meshes, {bm.nt} tets, {bm.nv} verts, setup {setup:.1f} s")
+    tuned = tune_batch(stream, meshes, E, nu)
+    bm.batch.fem.set_strategy(*tuned["chosen_raw"])
+    log(f"batch autotune: {tuned['chosen']} in {tuned['tune_s']} s")
     d0 = torch.zeros(3, bm.nv, dtype=torch.float64, device="cuda")
     d, v = d0.clone(), d0.clone()
     stats = torch.zeros(bm.nm, 3, dtype=torch.int64, device="cuda")
@@ -258,7 +267,37 @@ def bench_batch(stream, plain_rate):
             "tet_cg_iters_per_s": round(rate, 1),
             "vs_plain_tet_cg_iters_per_s": round(rate / plain_rate, 4) if plain_rate else None,
             "one_by_one": one,
-            "vs_one_by_one_tet_cg_iters_per_s": round(rate / one["tet_cg_iters_per_s"], 3)}
+            "vs_one_by_one_tet_cg_iters_per_s": round(rate / one["tet_cg_iters_per_s"], 3),
+            "autotune": {k: v for k, v in tuned.items() if k != "chosen_raw"}}
+
+
+def tune_batch(stream, meshes, E, nu):
+    """The autotuner on a batched union domain: every 16th mesh of the batch (16 meshes, sides,
+    E and nu as drawn), its stiffness product timed under every candidate; the choice is then
+    set on the whole batch.  (Tuning the whole 31.8M-tet union would rebuild its block tables
+    for every candidate, most of a minute.)"""
+    import torch
+
+    from paper_1506_07577_amd import ebbx
+    from paper_1506_07577_amd import meshgen as mg
+    sub = meshes[::16]
+    un = mg.union(sub)
+    bm = ebbx.BatchMesh(un, E[::16], nu[::16], model=ebbx.NH, elem_prec=ebbx.F32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = bm.batch.fem.autotune(stream=stream)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
+    names = {ebbx.STRAT_ATOMIC: "atomic", ebbx.STRAT_SEG: "seg", ebbx.STRAT_BLOCK: "block",
+             ebbx.STRAT_BLOCK_LDS: "block_lds", ebbx.STRAT_OWNER: "owner", ebbx.STRAT_PIPE: "pipe",
+             ebbx.STRAT_LANES: "lanes"}
+    chosen = bm.batch.fem.get_strategy()
+    out = {"sample": f"every 16th mesh of the batch: {len(sub)} meshes, {un.nt} tets",
+           "tune_s": round(tune_s, 2), "chosen": cand_name(names, chosen[0], chosen[1]), "chosen_raw": chosen,
+           "candidates_us": {cand_name(names, sid, blk): round(us, 2) for sid, blk, us in res},
+           "note": "stiffness product over the union, warm calls timed by the tuner (5 after 2 warm-up)"}
+    bm.batch.close()
+    return out
 
 
 def bench_one_by_one(stream, meshes, E, nu):

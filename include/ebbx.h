@@ -200,9 +200,14 @@ enum { EBBX_STVK = 0, EBBX_NH = 1 };
  * for BLOCK and BLOCK_LDS (64..256 for LANES), the owned vertices per block
  * (64, 128 or 256) for OWNER and the 256-tet blocks per workgroup (1..16) for
  * PIPE; 0 picks the
- * default (PIPE: 6, which on a Morton-ordered Kuhn mesh is 256 cells). */
+ * default (PIPE: 6, which on a Morton-ordered Kuhn mesh is 256 cells).
+ * Tets per thread, BLOCK and BLOCK_LDS: one, or two when the block size is
+ * or-ed with EBBX_BLOCK_TPT2 (a block of bt tets on bt/2 threads; bt of 128
+ * to 1024); blocks of 1024 tets always take two.  ebbx_fem_get_strategy
+ * returns the block argument as set, flag included. */
 enum { EBBX_STRAT_AUTO = 0, EBBX_STRAT_ATOMIC = 1, EBBX_STRAT_SEG = 2, EBBX_STRAT_BLOCK = 3,
        EBBX_STRAT_BLOCK_LDS = 4, EBBX_STRAT_OWNER = 5, EBBX_STRAT_PIPE = 6, EBBX_STRAT_LANES = 7 };
+#define EBBX_BLOCK_TPT2 0x10000
 
 typedef struct {
     int32_t model;       /* EBBX_STVK or EBBX_NH */

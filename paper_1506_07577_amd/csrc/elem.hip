@@ -695,7 +695,8 @@ static void launch_model(bool block, ElemOp op, int sc, int tpt, int w, int red,
 }
 
 bool elem_list_ok(const ebbx_fem_s *F, ElemOp op) {
-    return op == OP_KMUL && F->strategy == EBBX_STRAT_BLOCK && F->blk_red == 0 && F->blk_tets <= 512;
+    return op == OP_KMUL && F->strategy == EBBX_STRAT_BLOCK && F->blk_red == 0 && F->blk_tpt == 1 &&
+           F->blk_tets <= 512;
 }
 
 // The list-driven block kernel runs as many workgroups as fit on the device at once (a
@@ -861,8 +862,8 @@ void elem_launch(ebbx_fem_s *F, ElemOp op, const double *d, const double *u, dou
         if (shmem > lds_limit())
             fail(EBBX_E_STATE, "block strategy needs %zu bytes of LDS per block (%d vertices); reorder the mesh "
                  "(Morton) or use smaller blocks", shmem, F->blk_maxv);
-        const int threads = std::min(F->blk_tets, 512), tpt = F->blk_tets / threads;
-        if (tpt > 2) fail(EBBX_E_ARG, "block strategy: at most 1024 tets per block");
+        const int tpt = F->blk_tpt, threads = F->blk_tets / tpt;
+        if (threads > 512 || tpt > 2) fail(EBBX_E_ARG, "block strategy: at most 1024 tets per block");
         if (a.act && elem_list_ok(F, op)) {
             if (F->prec == EBBX_F32) {
                 if (F->model == EBBX_STVK) launch_block_list<float, EBBX_STVK>(F, a, threads, shmem, s);

@@ -196,6 +196,7 @@ struct ebbx_fem_s {
     ebbx::DevBuf B, V0, mat, mass, pinned, part, status, scratch, Xc;
     // block strategy tables
     int32_t blk_tets = 0;      // tets per block
+    int32_t blk_tpt = 1;       // tets per thread (block kernels run blk_tets / blk_tpt threads)
     int64_t nblk = 0;
     int32_t blk_maxv = 0;      // largest vertex count of one block
     int32_t blk_w = 1;         // 32-bit words of packed corner slots per tet

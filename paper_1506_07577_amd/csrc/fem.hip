@@ -82,14 +82,17 @@ void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s)
         return;
     }
     if (strategy == EBBX_STRAT_BLOCK || strategy == EBBX_STRAT_BLOCK_LDS || strategy == EBBX_STRAT_LANES) {
-        const int32_t bt = block ? block : 256;
+        const bool two = (block & EBBX_BLOCK_TPT2) != 0;
+        const int32_t bt = (block & ~EBBX_BLOCK_TPT2) ? (block & ~EBBX_BLOCK_TPT2) : 256;
         if (bt > 1024) fail(EBBX_E_ARG, "block strategies take at most 1024 tets per block");
-        if (strategy == EBBX_STRAT_LANES && bt > 256)
+        if (strategy == EBBX_STRAT_LANES && (bt > 256 || two))
             fail(EBBX_E_ARG, "the multi-lane product takes at most 256 tets per block (four lanes each)");
+        if (two && bt < 128) fail(EBBX_E_ARG, "two tets per thread need blocks of at least 128 tets");
         if (!F->blocks_built || F->blk_tets != bt || F->halo_level != 0) build_blocks(F, bt, s);
         F->strategy = strategy;
         F->blk_red = strategy == EBBX_STRAT_BLOCK_LDS ? 1 : 0;
-        F->block = bt;
+        F->blk_tpt = (two || bt > 512) ? 2 : 1;
+        F->block = two ? (bt | EBBX_BLOCK_TPT2) : bt;
         return;
     }
     if (block != 0 && (block < 64 || block > 256 || block % 64))

@@ -3,9 +3,9 @@
 // The paper reports that the solver kernels of its GPU runtime are sensitive
 // to the block size (up to 2x; Performance Evaluation, Vega) and that the
 // per-element matrix work is register-heavy (Discussion).  Here the choice
-// between scatter strategies and their block sizes is made by timing the
-// stiffness product, the call a CG iteration spends most of its time in, on
-// the domain itself.  Choices are cached in a small JSON file keyed by the
+// between scatter strategies, their block sizes and tets per thread is made
+// by timing the stiffness product, the call a CG iteration spends most of its
+// time in, on the domain itself.  Choices are cached in a small JSON file keyed by the
 // device, the element model and precision, the sizes and a fingerprint of
 // the tets' keys (locality decides between strategies).
 #include <algorithm>
@@ -34,6 +34,9 @@ const Candidate kCandidates[] = {
     {EBBX_STRAT_OWNER, 128},     {EBBX_STRAT_OWNER, 256},     {EBBX_STRAT_PIPE, 2},
     {EBBX_STRAT_PIPE, 4},        {EBBX_STRAT_PIPE, 6},        {EBBX_STRAT_PIPE, 8},
     {EBBX_STRAT_LANES, 64},      {EBBX_STRAT_LANES, 128},     {EBBX_STRAT_LANES, 256},
+    // two tets per thread
+    {EBBX_STRAT_BLOCK, 128 | EBBX_BLOCK_TPT2}, {EBBX_STRAT_BLOCK, 256 | EBBX_BLOCK_TPT2},
+    {EBBX_STRAT_BLOCK, 512 | EBBX_BLOCK_TPT2},
 };
 
 uint64_t fnv1a(const void *p, size_t n, uint64_t h) {

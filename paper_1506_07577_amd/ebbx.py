@@ -25,6 +25,7 @@ F32, F64, I32, U8, I64 = 0, 1, 2, 3, 4
 STVK, NH = 0, 1
 STRAT_AUTO, STRAT_ATOMIC, STRAT_SEG, STRAT_BLOCK, STRAT_BLOCK_LDS, STRAT_OWNER, STRAT_PIPE, STRAT_LANES = (
     0, 1, 2, 3, 4, 5, 6, 7)
+BLOCK_TPT2 = 0x10000   # or-ed into a BLOCK / BLOCK_LDS block size: two tets per thread
 PRECOND_NONE, PRECOND_JACOBI = 0, 1
 
 _DT = {torch.float32: F32, torch.float64: F64, torch.int32: I32, torch.uint8: U8, torch.int64: I64}
