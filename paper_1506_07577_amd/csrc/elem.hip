@@ -575,7 +575,10 @@ __global__ __launch_bounds__(256) void k_halo_tab(const double *halo, const int3
                                                   uint32_t S, double *o0, double *o1, double *o2, int accumulate,
                                                   const int *skip) {
     if (skip && *skip) return;
-    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
+    // XCD x sums one contiguous eighth of the shared vertices (sorted by id), those of its own
+    // eighth of the Morton-ordered blocks, whose halo entries that XCD wrote
+    const uint32_t wg = xcd_block(blockIdx.x, gridDim.x);
+    for (uint32_t s = wg * blockDim.x + threadIdx.x; s < S; s += gridDim.x * blockDim.x) {
         const uint32_t v = (uint32_t)sh_vert[s];
         int4 q[NC];
 #pragma unroll

@@ -9,6 +9,28 @@ namespace ebbx {
 
 enum ElemOp { OP_FORCE = 0, OP_KMUL = 1, OP_DIAG = 2, OP_TMUL = 3 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i on XCD i mod
+// 8), each XCD with its own L2.  Give XCD x one contiguous range of tet blocks,
+// so that neighbouring (Morton-adjacent) blocks, which share vertices, run under
+// the same L2.  A bijection of [0, nblk).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk) {
+    const uint32_t q = nblk >> 3, r = nblk & 7u, x = b & 7u, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
+// The same with runs of 2^k consecutive blocks dealt to the XCDs in turn (k > 0),
+// for a batch: there the blocks still working late in a solve are those of the
+// few meshes that iterate longest, one contiguous stretch that a single range per
+// XCD would leave to one XCD.  Blocks past the last whole round of 8 runs keep the
+// contiguous mapping.  A bijection of [0, nblk).
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk, uint32_t k) {
+    if (k == 0) return xcd_block(b, nblk);
+    const uint32_t full = (nblk >> (k + 3)) << (k + 3);
+    if (b >= full) return full + xcd_block(b - full, nblk - full);
+    const uint32_t x = b & 7u, i = b >> 3;
+    return ((((i >> k) << 3) + x) << k) + (i & ((1u << k) - 1u));
+}
+
 // The tet blocks of a batched solve still to evaluate, rebuilt from the meshes' finished flags
 // at the start of every CG iteration: one range per unfinished mesh, in mesh order.  hdr[0] is
 // the number of blocks, hdr[2] the number of unfinished meshes; range j covers list items

@@ -48,7 +48,15 @@ constexpr int VT = 256;   // threads of the vertex kernels = vertices per chunk
 // mesh[c]; the chunks of mesh m are [cptr[m], cptr[m+1]).
 struct Chunks {
     const int32_t *lo, *hi, *mesh, *cptr;
+    int xcd;   // 1: chunks dealt to the XCDs in contiguous ranges (one mesh), as its tet blocks are
 };
+
+// The chunk of this workgroup.  With one mesh, XCD x takes one contiguous eighth of the
+// chunks, the vertices of its eighth of the (Morton-ordered) tet blocks, so that a chunk's
+// vectors and its shared vertices' halo entries stay under one L2 from kernel to kernel.
+__device__ __forceinline__ int chunk_of(const Chunks &ch) {
+    return ch.xcd ? (int)xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+}
 
 static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + VT - 1) / VT)); }
 
@@ -238,7 +246,7 @@ __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, 
                                                  int precond, int mode, Chunks ch, double *part) {
     const double cm = 1.0 + dt * alpha, ck = dt * dt + dt * beta;
     __shared__ double s4[4];
-    const int c = blockIdx.x;
+    const int c = chunk_of(ch);
     const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
     double rz = 0.0, rr = 0.0;
     if (v < ch.hi[c]) {
@@ -333,7 +341,7 @@ __global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, con
                                               double cm, double ck, const CGState *st, Chunks ch, HaloView hv,
                                               double *part) {
     __shared__ double s4[4];
-    const int c = blockIdx.x;
+    const int c = chunk_of(ch);
     if (st[ch.mesh[c]].done) return;   // uniform over the block
     const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
     double pq = 0.0;
@@ -375,7 +383,7 @@ __global__ __launch_bounds__(VT) void k_cg_alpha(CGState *st, const double *part
 // x += alpha p; r -= alpha q; z = D^-1 r; chunk partials (r.z, r.r)
 __global__ __launch_bounds__(VT) void k_cg_update(StepVec w, int64_t nv, const CGState *st, Chunks ch, double *part) {
     __shared__ double s4[4];
-    const int c = blockIdx.x;
+    const int c = chunk_of(ch);
     const CGState &s = st[ch.mesh[c]];
     if (s.done) return;
     const double alpha = s.alpha;
@@ -426,7 +434,7 @@ __global__ __launch_bounds__(VT) void k_cg_beta(CGState *st, const double *part,
 
 // p = z + beta p
 __global__ __launch_bounds__(VT) void k_cg_p(StepVec w, int64_t nv, const CGState *st, Chunks ch) {
-    const int c = blockIdx.x;
+    const int c = chunk_of(ch);
     const CGState &s = st[ch.mesh[c]];
     if (s.done) return;
     const double beta = s.beta;
@@ -452,7 +460,7 @@ constexpr int FUSE_CHUNKS = 2048;
 __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGState *st, Chunks ch, double *part,
                                                     int par, SolveCtl *ctl) {
     __shared__ double s12[12];
-    const int c = blockIdx.x, m = ch.mesh[c];
+    const int c = chunk_of(ch), m = ch.mesh[c];
     if (st[m].done) return;   // uniform over the block
     const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
     const bool in = v < ch.hi[c];
@@ -509,7 +517,7 @@ __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGSta
 __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *st, Chunks ch, const double *part,
                                                int par, double tol, int maxit, SolveCtl *ctl) {
     __shared__ double s12[12];
-    const int c = blockIdx.x, m = ch.mesh[c];
+    const int c = chunk_of(ch), m = ch.mesh[c];
     if (st[m].done) return;   // uniform; a mesh marked done by its first chunk needs no new p
     const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
     const bool in = v < ch.hi[c];
@@ -563,7 +571,7 @@ __device__ __forceinline__ void write_stats(const CGState &s, double tol, ebbx_s
 // the first chunk of each mesh writes its stats record
 __global__ __launch_bounds__(VT) void k_step_end(StepVec w, int64_t nv, double dt, double tol, const CGState *st,
                                                  Chunks ch, double *d, double *v, ebbx_step_stats *stats) {
-    const int c = blockIdx.x, m = ch.mesh[c];
+    const int c = chunk_of(ch), m = ch.mesh[c];
     const CGState &s = st[m];
     const int64_t j = (int64_t)ch.lo[c] + threadIdx.x;
     if (s.status == EBBX_OK && j < ch.hi[c])
@@ -590,7 +598,7 @@ __global__ void k_vjp_prep(const double *d, const double *gx, const double *gv, 
 __global__ __launch_bounds__(VT) void k_vjp_end(StepVec w, const double *gx, const double *mass, double dt, double ck,
                                                 double dt_alpha, int64_t nv, const CGState *st, Chunks ch, double tol,
                                                 double *d_bar, double *v_bar, ebbx_step_stats *stats) {
-    const int c = blockIdx.x, m = ch.mesh[c];
+    const int c = chunk_of(ch), m = ch.mesh[c];
     const int64_t j = (int64_t)ch.lo[c] + threadIdx.x;
     if (j < ch.hi[c])
 #pragma unroll
@@ -868,7 +876,7 @@ void ensure_step(ebbx_fem_s *F, hipStream_t s) {
     HIPCHK(hipMemcpyAsync(cp + nch, hi.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(cp + 2 * nch, mesh.data(), nch * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(cp + 3 * nch, cptr.data(), (nm + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    S->ch = Chunks{cp, cp + nch, cp + 2 * nch, cp + 3 * nch};
+    S->ch = Chunks{cp, cp + nch, cp + 2 * nch, cp + 3 * nch, nm == 1 ? 1 : 0};
     S->part.reset((size_t)nch * 4 * sizeof(double), s);
     int32_t most = 0;
     for (int64_t m = 0; m < nm; ++m) most = std::max(most, cptr[(size_t)m + 1] - cptr[(size_t)m]);

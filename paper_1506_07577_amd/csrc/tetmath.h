@@ -345,28 +345,6 @@ template <class T, int MODEL> __device__ __forceinline__ bool diag12(T mu, T lam
 
 // ---- tet blocks -------------------------------------------------------------------
 
-// Workgroups are dispatched to the 8 XCDs round-robin (workgroup i on XCD i mod
-// 8), each XCD with its own L2.  Give XCD x one contiguous range of tet blocks,
-// so that neighbouring (Morton-adjacent) blocks, which share vertices, run under
-// the same L2.  A bijection of [0, nblk).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk) {
-    const uint32_t q = nblk >> 3, r = nblk & 7u, x = b & 7u, i = b >> 3;
-    return x * q + min(x, r) + i;
-}
-
-// The same with runs of 2^k consecutive blocks dealt to the XCDs in turn (k > 0),
-// for a batch: there the blocks still working late in a solve are those of the
-// few meshes that iterate longest, one contiguous stretch that a single range per
-// XCD would leave to one XCD.  Blocks past the last whole round of 8 runs keep the
-// contiguous mapping.  A bijection of [0, nblk).
-__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nblk, uint32_t k) {
-    if (k == 0) return xcd_block(b, nblk);
-    const uint32_t full = (nblk >> (k + 3)) << (k + 3);
-    if (b >= full) return full + xcd_block(b - full, nblk - full);
-    const uint32_t x = b & 7u, i = b >> 3;
-    return ((((i >> k) << 3) + x) << k) + (i & ((1u << k) - 1u));
-}
-
 // B = Dm^-1 and V0 = det(Dm)/6 of one tet from its corners' rest positions staged in
 // LDS (three columns of stride S): Dm from FP64 differences rounded to T, then the
 // adjugate over the determinant.  Recomputing B costs ~60 VALU per tet and saves the
