@@ -77,12 +77,13 @@ def _load():
     lib.orc_kinetic_energy.argtypes = [I64, P, P]
     lib.orc_kinetic_energy.restype = D
     lib.orc_morton.argtypes = [I64, I64, P, P, P, P, P]
+    lib.orc_morton_seg.argtypes = [I64, I64, P, P, P, P, P, P]
     lib.orc_forces_mt.argtypes = base + [P, P, P, P, P, C.c_int]
     lib.orc_kmul_mt.argtypes = base + [P, P, P, P, P, P, C.c_int]
     for f in ("orc_precompute", "orc_stress", "orc_dstress", "orc_d2stress",
               "orc_energy_density", "orc_forces", "orc_kmul", "orc_tmul", "orc_energy",
               "orc_jacobi_diag", "orc_implicit_step", "orc_step_vjp", "orc_group_by",
-              "orc_morton", "orc_edges", "orc_assemble", "orc_spmv", "orc_spring_rest",
+              "orc_morton", "orc_morton_seg", "orc_edges", "orc_assemble", "orc_spmv", "orc_spring_rest",
               "orc_spring_forces", "orc_spring_apply", "orc_forces_mt", "orc_kmul_mt"):
         getattr(lib, f).restype = C.c_int
     _lib = lib
@@ -210,14 +211,21 @@ class Springs:
         return _load().orc_kinetic_energy(self.nv, _p(self.mass), _p(qd))
 
 
-def morton(X: np.ndarray, tets: np.ndarray):
+def morton(X: np.ndarray, tets: np.ndarray, seg=None):
+    """Morton order (codes, vperm, tperm); with seg (one int label per vertex) the vertices are
+    ordered by (seg, code, id), a Morton order within each segment."""
     X = _f64(X)
     tets = np.ascontiguousarray(tets, dtype=np.int32)
     nv, nt = X.shape[0], tets.shape[0]
     codes = np.zeros(nv, dtype=np.uint64)
     vperm = np.zeros(nv, dtype=np.int32)
     tperm = np.zeros(nt, dtype=np.int32)
-    _chk(_load().orc_morton(nv, nt, _p(X), _p(tets), _p(codes), _p(vperm), _p(tperm)), "morton")
+    if seg is None:
+        _chk(_load().orc_morton(nv, nt, _p(X), _p(tets), _p(codes), _p(vperm), _p(tperm)), "morton")
+    else:
+        seg = np.ascontiguousarray(seg, dtype=np.int32)
+        assert seg.shape == (nv,)
+        _chk(_load().orc_morton_seg(nv, nt, _p(X), _p(tets), _p(seg), _p(codes), _p(vperm), _p(tperm)), "morton")
     return codes, vperm, tperm
 
 

@@ -881,8 +881,23 @@ int orc_group_by(int64_t nv, int64_t nt, const int32_t *tets, int64_t *row_ptr, 
     return ORC_OK;
 }
 
+typedef struct { int64_t seg; uint64_t code; int64_t id; } skv_t;
+
+static int skv_cmp(const void *a, const void *b) {
+    const skv_t *x = a, *y = b;
+    if (x->seg != y->seg) return x->seg < y->seg ? -1 : 1;
+    if (x->code != y->code) return x->code < y->code ? -1 : 1;
+    if (x->id != y->id) return x->id < y->id ? -1 : 1;
+    return 0;
+}
+
 int orc_morton(int64_t nv, int64_t nt, const double *X, const int32_t *tets,
                uint64_t *codes, int32_t *vperm, int32_t *tperm) {
+    return orc_morton_seg(nv, nt, X, tets, NULL, codes, vperm, tperm);
+}
+
+int orc_morton_seg(int64_t nv, int64_t nt, const double *X, const int32_t *tets, const int32_t *seg,
+                   uint64_t *codes, int32_t *vperm, int32_t *tperm) {
     double lo[3], hi[3], sc[3];
     for (int a = 0; a < 3; ++a) { lo[a] = INFINITY; hi[a] = -INFINITY; }
     for (int64_t v = 0; v < nv; ++v)
@@ -892,8 +907,9 @@ int orc_morton(int64_t nv, int64_t nt, const double *X, const int32_t *tets,
         }
     const double two21 = 2097152.0;
     for (int a = 0; a < 3; ++a) sc[a] = (hi[a] > lo[a]) ? two21 / (hi[a] - lo[a]) : 0.0;
-    kv_t *e = malloc(sizeof(kv_t) * (size_t)(nv > nt ? nv : nt));
-    if (!e) return ORC_E_ARG;
+    kv_t *e = malloc(sizeof(kv_t) * (size_t)(nt ? nt : 1));
+    skv_t *sv = malloc(sizeof(skv_t) * (size_t)(nv ? nv : 1));
+    if (!e || !sv) { free(e); free(sv); return ORC_E_ARG; }
     for (int64_t v = 0; v < nv; ++v) {
         uint64_t q[3], code = 0;
         for (int a = 0; a < 3; ++a) {
@@ -906,17 +922,19 @@ int orc_morton(int64_t nv, int64_t nt, const double *X, const int32_t *tets,
             for (int a = 0; a < 3; ++a)
                 code |= ((q[a] >> b) & 1ull) << (3 * b + a);
         codes[v] = code;
-        /* codes < 2^63, so the signed key keeps the order */
-        e[v].key = (int64_t)code;
-        e[v].val = v;
+        /* vertices in order of (segment, code, id); one segment when seg is NULL */
+        sv[v].seg = seg ? seg[v] : 0;
+        sv[v].code = code;
+        sv[v].id = v;
     }
-    qsort(e, (size_t)nv, sizeof(kv_t), kv_cmp);
+    qsort(sv, (size_t)nv, sizeof(skv_t), skv_cmp);
     int32_t *inv = malloc(sizeof(int32_t) * (size_t)(nv ? nv : 1));
-    if (!inv) { free(e); return ORC_E_ARG; }
+    if (!inv) { free(e); free(sv); return ORC_E_ARG; }
     for (int64_t i = 0; i < nv; ++i) {
-        vperm[i] = (int32_t)e[i].val;
-        inv[e[i].val] = (int32_t)i;
+        vperm[i] = (int32_t)sv[i].id;
+        inv[sv[i].id] = (int32_t)i;
     }
+    free(sv);
     for (int64_t t = 0; t < nt; ++t) {
         int32_t m = inv[tets[4 * t]];
         for (int c = 1; c < 4; ++c)

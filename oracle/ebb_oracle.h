@@ -136,6 +136,12 @@ int orc_kmul_mt(int model, int64_t nv, int64_t nt, const int32_t *tets,
  * corners, ties by old row). */
 int orc_morton(int64_t nv, int64_t nt, const double *X, const int32_t *tets,
                uint64_t *codes, int32_t *vperm, int32_t *tperm);
+/* The same with the vertices ordered by (seg[v], code, v): a Morton order within each segment
+ * (seg: one int32 label per vertex, e.g. the mesh of a batch).  The tets are then ordered as
+ * above, by their smallest new vertex id, so tets of one segment stay together when no tet
+ * spans two. */
+int orc_morton_seg(int64_t nv, int64_t nt, const double *X, const int32_t *tets, const int32_t *seg,
+                   uint64_t *codes, int32_t *vperm, int32_t *tperm);
 
 #ifdef __cplusplus
 }

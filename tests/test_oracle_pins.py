@@ -879,6 +879,33 @@ def test_morton_brute_force():
     assert np.all((c2.astype(object) & mask) == 0)
 
 
+def test_morton_segmented_brute_force():
+    """Morton order within segments: three jittered unit cubes of different resolutions in one
+    union, labelled by cube.  The vertices must come in order of (label, code, id), with
+    the codes from the union's one bounding box; the tets follow by their smallest new vertex, so
+    each cube's tets stay together; with one label the order is the plain one."""
+    cubes = [mg.jitter(mg.kuhn_cube(n), 0.01, seed=20 + i) for i, n in enumerate((2, 3, 2))]
+    un = mg.union(cubes)
+    # the cubes overlap in space, so only the labels keep their vertices apart
+    seg = np.asarray(un.vert_mesh, dtype=np.int32)
+    codes, vperm, tperm = oracle.morton(un.X, un.tets, seg=seg)
+    assert np.array_equal(codes, _naive_morton(un.X))
+    order = sorted(range(un.nv), key=lambda v: (int(seg[v]), int(codes[v]), v))
+    assert np.array_equal(vperm, order)
+    inv = np.empty(un.nv, dtype=np.int64)
+    inv[vperm] = np.arange(un.nv)
+    key = inv[un.tets].min(axis=1)
+    assert np.array_equal(tperm, sorted(range(un.nt), key=lambda t: (key[t], t)))
+    # each cube's vertices and tets stay contiguous and in cube order
+    assert np.all(np.diff(seg[vperm]) >= 0)
+    tseg = np.asarray(un.tet_mesh)[tperm]
+    assert np.all(np.diff(tseg) >= 0)
+    # a single label gives the plain Morton order
+    c1, v1, t1 = oracle.morton(un.X, un.tets, seg=np.zeros(un.nv, dtype=np.int32))
+    c0, v0, t0 = oracle.morton(un.X, un.tets)
+    assert np.array_equal(v1, v0) and np.array_equal(t1, t0) and np.array_equal(c1, c0)
+
+
 # --------------------------------------------------------------------------
 # multi-threaded timing entries of the oracle
 # --------------------------------------------------------------------------
