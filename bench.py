@@ -219,8 +219,8 @@ def bench_autotune(stream, n):
 
 
 def bench_batch(stream, plain_rate):
-    """256 Kuhn cubes (sides 8..40), neo-Hookean, FP32 elements, per-mesh E and nu,
-    one implicit step of every mesh with per-mesh CG to 1e-8 (maxit 1000)."""
+    """256 Kuhn cubes (sides 8..40), neo-Hookean, FP32 elements, per-mesh E and nu, each mesh in
+    lattice order, one implicit step of every mesh with per-mesh CG to 1e-8 (maxit 1000)."""
     import torch
 
     from paper_1506_07577_amd import ebbx

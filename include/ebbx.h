@@ -136,14 +136,18 @@ ebbx_status ebbx_group_export(ebbx_relation rel, const char *keyfield, int64_t *
  * runtime may reorder relations).  From the FP64 (3, nv) field `pos_field`
  * of verts: per-axis bounding box [lo, hi], q = min(2^21-1, floor((x-lo) *
  * (2^21/(hi-lo)))) (q = 0 on a flat axis), bit b of q_x, q_y, q_z at bits
- * 3b, 3b+1, 3b+2 of a uint64 code; vertices sorted by (code, old id).  Rows
- * of rel are then sorted by (min over slots of the new vertex id of key-field
- * `keyfield`, old row).  Outputs (device, nullable): codes_dev[nv] (uint64),
- * vperm_dev[nv] and tperm_dev[size(rel)], each mapping new -> old.  Nothing
- * is permuted.  Synchronous. */
-ebbx_status ebbx_morton_order(ebbx_relation verts, const char *pos_field, ebbx_relation rel,
-                              const char *keyfield, uint64_t *codes_dev, int32_t *vperm_dev,
-                              int32_t *tperm_dev);
+ * 3b, 3b+1, 3b+2 of a uint64 code; vertices sorted by (code, old id).  With
+ * seg_keyfield (nullable), an arity-1 key-field of verts (e.g. the mesh of
+ * each vertex of a batch), the vertices are sorted by (segment, code, old id)
+ * instead: a Morton order within each segment, the segments in key order, so
+ * a batch's meshes stay contiguous (codes still use the one bounding box of
+ * all vertices).  Rows of rel are then sorted by (min over slots of the new
+ * vertex id of key-field `keyfield`, old row).  Outputs (device, nullable):
+ * codes_dev[nv] (uint64), vperm_dev[nv] and tperm_dev[size(rel)], each
+ * mapping new -> old.  Nothing is permuted.  Synchronous. */
+ebbx_status ebbx_morton_order(ebbx_relation verts, const char *pos_field, const char *seg_keyfield,
+                              ebbx_relation rel, const char *keyfield, uint64_t *codes_dev,
+                              int32_t *vperm_dev, int32_t *tperm_dev);
 
 /* Permute rel in place by new_to_old_dev (a permutation of [0, size)): every
  * bound field and key-field of rel is gathered row-wise, and every key-field

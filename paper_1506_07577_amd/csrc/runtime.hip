@@ -425,6 +425,13 @@ __global__ void k_morton_codes(const double *X, int64_t nv, MortonFrame fr, uint
     }
 }
 
+// out[i] = key[ids[i]]: the sort keys of a permutation's entries
+__global__ void k_gather_key(const int32_t *key, const uint32_t *ids, int64_t n, uint32_t *out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (uint32_t)key[ids[i]];
+}
+
 __global__ void k_invert(const uint32_t *perm, int64_t n, int32_t *inv) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -622,14 +629,20 @@ ebbx_status ebbx_group_export(ebbx_relation rel, const char *keyfield, int64_t *
     EBBX_API_END
 }
 
-ebbx_status ebbx_morton_order(ebbx_relation verts, const char *pos_field, ebbx_relation rel, const char *keyfield,
-                              uint64_t *codes_dev, int32_t *vperm_dev, int32_t *tperm_dev) {
+ebbx_status ebbx_morton_order(ebbx_relation verts, const char *pos_field, const char *seg_keyfield,
+                              ebbx_relation rel, const char *keyfield, uint64_t *codes_dev, int32_t *vperm_dev,
+                              int32_t *tperm_dev) {
     EBBX_API_BEGIN
     auto *vr = check_rel(verts);
     auto *tr = check_rel(rel);
     const Field &X = get_field(vr, pos_field, EBBX_F64, 3);
     KeyField &kf = get_key(tr, keyfield);
     if (kf.target != vr) fail(EBBX_E_ARG, "key-field '%s' does not target '%s'", keyfield, vr->name.c_str());
+    const KeyField *seg = nullptr;
+    if (seg_keyfield) {
+        seg = &get_key(vr, seg_keyfield);
+        if (seg->arity != 1) fail(EBBX_E_SHAPE, "segment key-field '%s' must have arity 1", seg_keyfield);
+    }
     const int64_t nv = vr->size, nt = tr->size;
     hipStream_t s = nullptr;
     // bounding box
@@ -662,6 +675,13 @@ ebbx_status ebbx_morton_order(ebbx_relation verts, const char *pos_field, ebbx_r
         if (codes_dev)
             HIPCHK(hipMemcpyAsync(codes_dev, codes.get(), (size_t)nv * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
         radix_sort_pairs_u64(codes.as<uint64_t>(), vids.as<uint32_t>(), nv, 63, s);
+        if (seg) {   // then a stable sort by segment: (segment, code, id)
+            DevBuf sk((size_t)nv * sizeof(uint32_t), s);
+            hipLaunchKernelGGL(k_gather_key, dim3(grid_for(nv, 256, 16384)), dim3(256), 0, s, seg->ptr,
+                               vids.as<uint32_t>(), nv, sk.as<uint32_t>());
+            HIPCHK(hipGetLastError());
+            radix_sort_pairs_u32(sk.as<uint32_t>(), vids.as<uint32_t>(), nv, bits_for(seg->target->size), s);
+        }
     }
     if (vperm_dev && nv > 0)
         HIPCHK(hipMemcpyAsync(vperm_dev, vids.get(), (size_t)nv * sizeof(int32_t), hipMemcpyDeviceToDevice, s));

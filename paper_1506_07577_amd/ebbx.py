@@ -98,7 +98,7 @@ def lib():
         "ebbx_keyfield_bind": ([P, S, P, I32_, P], I32_),
         "ebbx_relation_group_by": ([P, S], I32_),
         "ebbx_group_export": ([P, S, P, P], I32_),
-        "ebbx_morton_order": ([P, S, P, S, P, P, P], I32_),
+        "ebbx_morton_order": ([P, S, S, P, S, P, P, P], I32_),
         "ebbx_relation_reorder": ([P, P], I32_),
         "ebbx_fem_create": ([P, S, P, S, S, C.POINTER(FemParams), C.POINTER(P)], I32_),
         "ebbx_fem_destroy": ([P], I32_),
@@ -234,13 +234,14 @@ class Relation:
             self.h = None
 
 
-def morton_order(verts: Relation, pos_field: str, rel: Relation, keyfield: str):
-    """Returns (codes uint64-as-int64, vperm int32, tperm int32), each new -> old."""
+def morton_order(verts: Relation, pos_field: str, rel: Relation, keyfield: str, seg: Optional[str] = None):
+    """Returns (codes uint64-as-int64, vperm int32, tperm int32), each new -> old.  seg: an
+    arity-1 key-field of verts whose segments (e.g. a batch's meshes) the order keeps apart."""
     codes = torch.empty(max(verts.size, 1), dtype=torch.int64, device="cuda")
     vperm = torch.empty(max(verts.size, 1), dtype=torch.int32, device="cuda")
     tperm = torch.empty(max(rel.size, 1), dtype=torch.int32, device="cuda")
-    _check(lib().ebbx_morton_order(verts.h, pos_field.encode(), rel.h, keyfield.encode(), _ptr(codes),
-                                   _ptr(vperm), _ptr(tperm)))
+    _check(lib().ebbx_morton_order(verts.h, pos_field.encode(), seg.encode() if seg else None, rel.h,
+                                   keyfield.encode(), _ptr(codes), _ptr(vperm), _ptr(tperm)))
     return codes[: verts.size], vperm[: verts.size], tperm[: rel.size]
 
 
@@ -520,9 +521,15 @@ class Batch:
 
 
 class BatchMesh:
-    """Convenience: upload a meshgen.MeshUnion with per-mesh E and nu and build its Batch."""
+    """Convenience: upload a meshgen.MeshUnion with per-mesh E and nu and build its Batch.
 
-    def __init__(self, un, E, nu, model=NH, elem_prec=F32, rho=1000.0, strategy=STRAT_BLOCK, block=0):
+    morton=True reorders the union into a Morton order within each mesh (the runtime's
+    ebbx_morton_order with the verts' mesh key-field as segments, then ebbx_relation_reorder),
+    which keeps the meshes contiguous as a batch requires; to_dev and from_dev translate between
+    the caller's vertex order and the library's."""
+
+    def __init__(self, un, E, nu, model=NH, elem_prec=F32, rho=1000.0, strategy=STRAT_BLOCK, block=0,
+                 morton=False):
         self.un = un
         nm = len(un.vptr) - 1
         self.meshes = Relation("meshes", nm)
@@ -535,17 +542,31 @@ class BatchMesh:
         self.verts.bind_keyfield("mesh", self.meshes, torch.as_tensor(un.vert_mesh).to(torch.int32).cuda())
         self.tets.bind_keyfield("v", self.verts, torch.as_tensor(un.tets).to(torch.int32).t().contiguous().cuda())
         self.tets.bind_keyfield("mesh", self.meshes, torch.as_tensor(un.tet_mesh).to(torch.int32).cuda())
+        self.vperm = self.tperm = None
+        if morton:
+            _codes, self.vperm, self.tperm = morton_order(self.verts, "X", self.tets, "v", seg="mesh")
+            self.verts.reorder(self.vperm)
+            self.tets.reorder(self.tperm)
         self.batch = Batch(self.meshes, self.tets, self.verts, model, elem_prec, rho=rho, strategy=strategy,
                            block=block)
         self.fem = self.batch.fem
         self.nm, self.nv, self.nt = nm, un.nv, un.nt
 
     def to_dev(self, a):
-        return torch.as_tensor(a, dtype=torch.float64).t().contiguous().cuda()
+        """(nv, 3) array in the union's vertex order -> (3, nv) device tensor in library order."""
+        t = torch.as_tensor(a, dtype=torch.float64)
+        if self.vperm is not None:
+            t = t[self.vperm.cpu().long()]
+        return t.t().contiguous().cuda()
 
-    @staticmethod
-    def from_dev(t):
-        return t.t().cpu().numpy()
+    def from_dev(self, t):
+        """(3, nv) device tensor in library order -> (nv, 3) numpy in the union's vertex order."""
+        a = t.t().cpu().numpy()
+        if self.vperm is not None:
+            out = a.copy()
+            out[self.vperm.cpu().numpy()] = a
+            a = out
+        return a
 
 
 def stats_parse(stats_dev: torch.Tensor):

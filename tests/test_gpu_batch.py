@@ -64,12 +64,14 @@ def _oracle_steps(meshes, un, E, nu, d, v, dt, tol, maxit, model):
     return out_d, out_v, stats
 
 
+@pytest.mark.parametrize("morton", [False, True])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("model", [ebbx.NH if ebbx else 1, ebbx.STVK if ebbx else 0])
-def test_batch_step_parity(prec, model):
+def test_batch_step_parity(prec, model, morton):
+    """Lattice order, and Morton order within each mesh (the union reordered by the runtime)."""
     meshes, E, nu = _small_batch()
     un = mg.union(meshes)
-    bm = ebbx.BatchMesh(un, E, nu, model=model, elem_prec=ebbx.F64 if prec == "f64" else ebbx.F32)
+    bm = ebbx.BatchMesh(un, E, nu, model=model, elem_prec=ebbx.F64 if prec == "f64" else ebbx.F32, morton=morton)
     d, v = _states(un)
     dt, tol = 1e-3, (1e-12 if prec == "f64" else 1e-8)
     dd, vv = bm.to_dev(d), bm.to_dev(v)
