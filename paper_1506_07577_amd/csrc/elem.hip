@@ -180,7 +180,15 @@ __device__ __forceinline__ void block_body(const ElemArgs &a, uint32_t blk, uint
     // positions and recompute B per tet; others stream the stored B (their vertex gathers are
     // scattered, and the 24 B per block vertex would cost more than the 36-72 B per tet)
     constexpr bool XB = W == 1;
+    // FP32 elements stage the block-local FP32 rest positions of a precomputed table (read
+    // contiguously, without waiting for the block's vertex ids) instead of gathering X
+    constexpr bool XF = XB && sizeof(T) == 4;
     double *s_x = s_d + 3 * NQ * S;   // rest positions of the block's vertices (XB)
+    float *s_xf = (float *)s_x;       // their block-local FP32 form (XF)
+    const float *xf[3] = {nullptr, nullptr, nullptr};
+    if (XF)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xf[k] = a.xf[k] + (size_t)blk * S;
     T *s_h = (T *)(s_x + (XB ? 3 * S : 0));   // rows (moved to the LDS start when REUSE)
     double *s_acc = (double *)s_h;
 
@@ -226,7 +234,8 @@ __device__ __forceinline__ void block_body(const ElemArgs &a, uint32_t blk, uint
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * S + tid] = ldc<double>(a.d[k], gv0);
-            if (XB) s_x[k * S + tid] = ldc<double>(a.X[k], gv0);
+            if (XF) s_xf[k * S + tid] = xf[k][tid];
+            else if (XB) s_x[k * S + tid] = ldc<double>(a.X[k], gv0);
             if (NQ > 1) s_u[k * S + tid] = ldc<double>(a.u[k], gv0);
             if (NQ > 2) s_w[k * S + tid] = ldc<double>(a.w[k], gv0);
             if (RED == 1) s_acc[k * S + tid] = 0.0;
@@ -239,7 +248,8 @@ __device__ __forceinline__ void block_body(const ElemArgs &a, uint32_t blk, uint
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             s_d[k * S + i] = ldc<double>(a.d[k], gv);
-            if (XB) s_x[k * S + i] = ldc<double>(a.X[k], gv);
+            if (XF) s_xf[k * S + i] = xf[k][i];
+            else if (XB) s_x[k * S + i] = ldc<double>(a.X[k], gv);
             if (NQ > 1) s_u[k * S + i] = ldc<double>(a.u[k], gv);
             if (NQ > 2) s_w[k * S + i] = ldc<double>(a.w[k], gv);
             if (RED == 1) s_acc[k * S + i] = 0.0;
@@ -311,7 +321,8 @@ __device__ __forceinline__ void block_body(const ElemArgs &a, uint32_t blk, uint
                         qu[c][k] = (NQ > 1) ? s_u[k * S + sl[r][c]] : 0.0;
                         qw[c][k] = (NQ > 2) ? s_w[k * S + sl[r][c]] : 0.0;
                     }
-                if (XB) rest_B(s_x, S, sl[r], b[r], V0[r]);
+                if constexpr (XF) rest_B_local(s_xf, S, sl[r], b[r], V0[r]);
+                else if (XB) rest_B(s_x, S, sl[r], b[r], V0[r]);
                 T h[12];
                 const bool ok = eval_tet<T, MODEL, OP>(mu[r], lam[r], b[r], V0[r], qd, qu, h, qw);
                 if (MODEL == EBBX_NH && OP == OP_FORCE && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
@@ -748,6 +759,8 @@ static ElemArgs base_args(ebbx_fem_s *F) {
     a.slot[1] = F->blk_local.as<uint32_t>() + (F->blk_w == 2 ? nt : 0);
     a.halo = F->halo.as<double>();
     a.nblk = (uint32_t)F->nblk;
+    for (int k = 0; k < 3; ++k)
+        a.xf[k] = F->blk_xf.get() ? F->blk_xf.as<float>() + (size_t)k * F->nblk * F->blk_maxv : nullptr;
     // a batch deals runs of 64 blocks to the XCDs in turn (see xcd_block; runs of 16, 64
     // and 256 blocks measured 19.0, 19.1 and 19.5 ms per 256-mesh step against 20.8 ms
     // for one range per XCD); one mesh keeps one range per XCD
@@ -1337,6 +1350,17 @@ void build_halo(ebbx_fem_s *F, const std::vector<int32_t> &verts, const std::vec
 // vertices at [b*maxv, (b+1)*maxv) padded with -1 (halo positions hpos alike) and
 // its block-relative row starts at [b*(maxv+1), (b+1)*(maxv+1)); per tet the corner
 // rows and the packed slots.
+// Block-local FP32 rest positions: entry (b, i) holds X of block b's i-th vertex minus X of its
+// first vertex, rounded to FP32 (three columns of nblk * S entries; padding 0).
+__global__ void k_block_xf(const double *X, int64_t nv, const int32_t *bverts, int64_t n, uint32_t S, float *xf) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = bverts[e], v0 = bverts[(e / S) * S];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            xf[(int64_t)k * n + e] = v >= 0 ? (float)(X[(int64_t)k * nv + v] - X[(int64_t)k * nv + v0]) : 0.0f;
+    }
+}
+
 void upload_block_tables(ebbx_fem_s *F, const HostBlocks &hb, const std::vector<int32_t> &hpos, hipStream_t s) {
     const int64_t nblk = hb.nblk;
     const size_t S = (size_t)hb.maxv;
@@ -1367,6 +1391,16 @@ void upload_block_tables(ebbx_fem_s *F, const HostBlocks &hb, const std::vector<
     F->blk_maxv = hb.maxv;
     F->blk_w = hb.w;
     F->blk_nverts = (int64_t)hb.verts.size();
+    // FP32 elements on blocks of at most 256 vertices read block-local FP32 rest positions
+    if (F->prec == EBBX_F32 && hb.w == 1 && nblk > 0) {
+        const int64_t n = nblk * (int64_t)S;
+        F->blk_xf.reset((size_t)n * 3 * sizeof(float), s);
+        hipLaunchKernelGGL(k_block_xf, dim3(grid_n(n, 256, 16384)), dim3(256), 0, s, F->Xc.as<double>(), F->nv,
+                           F->blk_verts.as<int32_t>(), n, (uint32_t)S, F->blk_xf.as<float>());
+        HIPCHK(hipGetLastError());
+    } else {
+        F->blk_xf.release();
+    }
 }
 
 void download_keys(const ebbx_fem_s *F, std::vector<int32_t> &keys, std::vector<int64_t> &rp) {

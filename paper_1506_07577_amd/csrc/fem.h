@@ -71,6 +71,8 @@ struct ElemArgs {
     uint32_t blk_stride;
     const uint32_t *slot[2];    // packed corner slots within the block (one or two words per tet)
     double *halo;               // partial sums of shared vertices, 3 per entry, block-major
+    const float *xf[3];         // FP32 elements, blocks of <= 256 vertices: block-local rest positions
+                                // (stride blk_stride per block), or NULL
     uint32_t nblk;              // tet blocks
     // PIPE strategy
     const uint32_t *blk_run;    // per block vertex (stride blk_stride): run start | run end << 11 | acc index << 22
@@ -226,6 +228,7 @@ struct ebbx_fem_s {
     int64_t blk_nverts = 0;    // entries of blk_verts over all blocks
     int64_t sh_n = 0;          // vertices summed from the halo (shared or untouched)
     int64_t halo_n = 0;        // halo entries
+    ebbx::DevBuf blk_xf;   // block-local FP32 rest positions (FP32 elements, blocks of <= 256 vertices)
     ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_pos, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos, sh_tab,
         sh_row;
     int32_t sh_nc = 0;         // int4 chunks per row of sh_tab (0: use the CSR form)

@@ -373,6 +373,31 @@ __device__ __forceinline__ void rest_B(const double *s_x, uint32_t S, const uint
     V0 = det * T(1.0 / 6.0);
 }
 
+// The same from block-local FP32 rest positions (each block vertex's offset from the block's
+// first vertex, precomputed once): Dm from FP32 differences of the offsets.
+__device__ __forceinline__ void rest_B_local(const float *s_xf, uint32_t S, const uint32_t *sl, float *b, float &V0) {
+    float x0[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) x0[k] = s_xf[k * S + sl[0]];
+    float Dm[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) Dm[3 * k + c] = s_xf[k * S + sl[c + 1]] - x0[k];
+    const float det = det3(Dm);
+    const float idet = t_rcp(det);
+    b[0] = (Dm[4] * Dm[8] - Dm[5] * Dm[7]) * idet;
+    b[1] = (Dm[2] * Dm[7] - Dm[1] * Dm[8]) * idet;
+    b[2] = (Dm[1] * Dm[5] - Dm[2] * Dm[4]) * idet;
+    b[3] = (Dm[5] * Dm[6] - Dm[3] * Dm[8]) * idet;
+    b[4] = (Dm[0] * Dm[8] - Dm[2] * Dm[6]) * idet;
+    b[5] = (Dm[2] * Dm[3] - Dm[0] * Dm[5]) * idet;
+    b[6] = (Dm[3] * Dm[7] - Dm[4] * Dm[6]) * idet;
+    b[7] = (Dm[1] * Dm[6] - Dm[0] * Dm[7]) * idet;
+    b[8] = (Dm[0] * Dm[4] - Dm[1] * Dm[3]) * idet;
+    V0 = det * (1.0f / 6.0f);
+}
+
 // ---- gather / element evaluation ----------------------------------------------------
 
 // M = dD B with dD = [q1-q0 | q2-q0 | q3-q0]; differences in FP64, then rounded to T
