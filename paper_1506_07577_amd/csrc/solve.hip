@@ -159,8 +159,9 @@ __device__ __forceinline__ void mark_done(CGState &st, SolveCtl *ctl, int m) {
 
 // Rebuild the active list (ActList) of a batched solve from the meshes' finished flags, at the
 // start of a CG iteration; one workgroup.  Mesh m's tets are [tptr[m], tptr[m+1]), its blocks
-// of bt tets those holding them; a block it shares with an earlier unfinished mesh is that
-// mesh's.  Scans are in mesh order, so the list is the same on every run.
+// of bt tets those holding them; its first block is left to an earlier unfinished mesh with
+// tets in that block, if there is one (small meshes can share a block with several others).
+// Scans are in mesh order, so the list is the same on every run.
 __global__ __launch_bounds__(VT) void k_active(const SolveCtl *ctl, const int64_t *tptr, const int32_t *tmesh,
                                                int32_t nm, int32_t bt, int32_t *act) {
     __shared__ int32_t s_x[2][VT];
@@ -176,7 +177,8 @@ __global__ __launch_bounds__(VT) void k_active(const SolveCtl *ctl, const int64_
             const int64_t t0 = tptr[m], t1 = tptr[m + 1];
             if (t1 > t0) {
                 const int64_t b0 = t0 / bt, b1 = (t1 - 1) / bt + 1;
-                const bool taken = t0 > 0 && (t0 - 1) / bt == b0 && !done[tmesh[t0 - 1]];
+                bool taken = false;
+                for (int32_t mm = tmesh[b0 * bt]; mm < m && !taken; ++mm) taken = !done[mm];
                 bs = (int32_t)(b0 + (taken ? 1 : 0));
                 nb = (int32_t)(b1 - bs);
             }

@@ -142,6 +142,51 @@ def test_batch_per_mesh_outcomes():
         assert nerr(gv[a:b], ev[j]) < 1e-8
 
 
+def test_batch_many_small_meshes():
+    """300 meshes of 1 to 3 cells a side (6 to 162 tets; up to dozens of meshes share one 256-tet
+    block), a few of them fully pinned (finished before the first iteration) and two with an
+    inverted tet: the block lists of the batched solve span two tiles of meshes, keep every block
+    that an unfinished mesh touches and list it once, whichever meshes around it have finished.
+    Every mesh matches the oracle (FP64, 1e-9) or reports its own outcome."""
+    rng = np.random.default_rng(21)
+    sides = rng.integers(1, 4, 300)
+    meshes, E, nu = _small_batch(sides=tuple(int(x) for x in sides), seed=22)
+    pinned = set(int(i) for i in rng.choice(300, 25, replace=False))
+    for i in pinned:
+        meshes[i].pinned[:] = 1
+    un = mg.union(meshes)
+    bm = ebbx.BatchMesh(un, E, nu, model=ebbx.NH, elem_prec=ebbx.F64)
+    d, v = _states(un, seed=23)
+    for i in pinned:
+        d[un.vptr[i]:un.vptr[i + 1]] = 0.0
+        v[un.vptr[i]:un.vptr[i + 1]] = 0.0
+    inverted = [i for i in (7, 151) if i not in pinned]
+    for i in inverted:
+        t = un.tets[un.tptr[i]]
+        x = un.X[t]
+        d[t[3]] = 2.0 * (x[:3].mean(axis=0) - x[3])
+    dd, vv = bm.to_dev(d), bm.to_dev(v)
+    st = ebbx.stats_parse(bm.batch.implicit_step(dd, vv, 1e-3, tol=1e-12, maxit=400))
+    gv = bm.from_dev(vv)
+    iters = set()
+    for i, m in enumerate(meshes):
+        a, b = un.vptr[i], un.vptr[i + 1]
+        if i in inverted:
+            assert st[i].status == ebbx.E_INVERTED, i
+            assert np.array_equal(gv[a:b], v[a:b]), i
+            continue
+        assert st[i].status == ebbx.OK, (i, st[i].status)
+        if i in pinned:
+            assert st[i].iters == 0 and np.all(gv[a:b] == 0.0), i
+            continue
+        iters.add(st[i].iters)
+        ref = oracle.FEM.create(ebbx.NH, m.X, m.tets, E[i], nu[i], pinned=m.pinned)
+        _d1, v1, _dv, _s = ref.implicit_step(d[a:b], v[a:b], 1e-3, tol=1e-12, maxit=400)
+        assert nerr(gv[a:b], v1) < 1e-9, i
+    assert len(iters) > 3   # meshes finish at different iterations
+    bm.batch.close()
+
+
 def test_batch_element_maps_cover_every_block():
     """The union's force and stiffness maps (block strategy) over a batch of 815 tet blocks:
     batches deal runs of 64 blocks to the XCDs in turn and map the blocks past the last whole
