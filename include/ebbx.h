@@ -200,8 +200,8 @@ enum { EBBX_STVK = 0, EBBX_NH = 1 };
  *   AUTO:      BLOCK with 256 tets per block (ebbx_fem_autotune times the
  *              alternatives on the domain itself).
  * The `block` argument of the calls below is the workgroup size (threads) for
- * ATOMIC and SEG, the number of tets per block (64..1024, a power of two)
- * for BLOCK and BLOCK_LDS (64..256 for LANES), the owned vertices per block
+ * ATOMIC and SEG, the number of tets per block (a multiple of 64 from 64 to
+ * 1024) for BLOCK and BLOCK_LDS (64..256 for LANES), the owned vertices per block
  * (64, 128 or 256) for OWNER and the 256-tet blocks per workgroup (1..16) for
  * PIPE; 0 picks the
  * default (PIPE: 6, which on a Morton-ordered Kuhn mesh is 256 cells).

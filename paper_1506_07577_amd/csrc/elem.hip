@@ -1412,8 +1412,8 @@ void download_keys(const ebbx_fem_s *F, std::vector<int32_t> &keys, std::vector<
 
 // The BLOCK tables with a halo of the blocks' shared vertices.
 void build_blocks(ebbx_fem_s *F, int32_t bt, hipStream_t s) {
-    if (bt != 64 && bt != 128 && bt != 256 && bt != 512 && bt != 1024)
-        fail(EBBX_E_ARG, "block strategy: tets per block must be 64, 128, 256, 512 or 1024 (got %d)", bt);
+    if (bt < 64 || bt > 1024 || bt % 64)
+        fail(EBBX_E_ARG, "block strategy: tets per block must be a multiple of 64 from 64 to 1024 (got %d)", bt);
     std::vector<int32_t> keys;
     std::vector<int64_t> rp;
     download_keys(F, keys, rp);

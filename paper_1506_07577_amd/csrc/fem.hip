@@ -50,7 +50,7 @@ const char *fem_relation_user(const ebbx_relation_s *r) {
 }
 
 // `block`: threads per workgroup for ATOMIC and SEG (64..256, multiple of 64);
-// tets per block for BLOCK (64, 128, 256, 512 or 1024).  0 = default.
+// tets per block for BLOCK (a multiple of 64 from 64 to 1024).  0 = default.
 void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s) {
     if (strategy < EBBX_STRAT_AUTO || strategy > EBBX_STRAT_LANES) fail(EBBX_E_ARG, "bad strategy %d", strategy);
     // captured solver graphs hold pointers into the block, halo and owner tables that the
@@ -88,6 +88,8 @@ void set_strategy(ebbx_fem_s *F, int32_t strategy, int32_t block, hipStream_t s)
         if (strategy == EBBX_STRAT_LANES && (bt > 256 || two))
             fail(EBBX_E_ARG, "the multi-lane product takes at most 256 tets per block (four lanes each)");
         if (two && bt < 128) fail(EBBX_E_ARG, "two tets per thread need blocks of at least 128 tets");
+        if ((two || bt > 512) && bt % 128)
+            fail(EBBX_E_ARG, "two tets per thread need a multiple of 128 tets per block (got %d)", bt);
         if (!F->blocks_built || F->blk_tets != bt || F->halo_level != 0) build_blocks(F, bt, s);
         F->strategy = strategy;
         F->blk_red = strategy == EBBX_STRAT_BLOCK_LDS ? 1 : 0;

@@ -451,6 +451,32 @@ def test_empty_and_isolated(strat):
     mesh.fem.close()
 
 
+@pytest.mark.parametrize("blk", [192, 384, 640, 384 | 0x10000])
+def test_block_sizes_multiple_of_64(blk):
+    """Blocks of any multiple of 64 tets (here not powers of two, and two tets per thread), FP64
+    neo-Hookean on a jittered Morton-ordered 10^3 cube: force, K u and one step against the oracle
+    (1e-10); sizes that are not multiples of 64 (or of 128 with two tets per thread) are refused."""
+    m = mg.jitter(mg.kuhn_cube(10), 0.01, seed=3)
+    mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.NH, elem_prec=ebbx.F64, E=1e5, nu=0.3,
+                        strategy=ebbx.STRAT_BLOCK, block=blk, morton=True)
+    assert mesh.fem.get_strategy() == (ebbx.STRAT_BLOCK, blk)
+    ref = oracle.FEM.create(ebbx.NH, m.X, m.tets, 1e5, 0.3, pinned=m.pinned)
+    d = mg.perturbed_state(m, 0.02, seed=10)
+    u = mg.direction(m, 11)
+    assert nerr(mesh.from_dev(mesh.fem.forces(mesh.to_dev(d))), ref.forces(d)) <= 1e-10
+    assert nerr(mesh.from_dev(mesh.fem.kmul(mesh.to_dev(d), mesh.to_dev(u))), ref.kmul(d, u)) <= 1e-10
+    dd, vv = mesh.to_dev(d), mesh.to_dev(np.zeros_like(d))
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(dd, vv, 1e-3, tol=0.0, maxit=30))
+    _d1, v1, _dv, _so = ref.implicit_step(d, np.zeros_like(d), 1e-3, tol=0.0, maxit=30)
+    assert s.status == ebbx.OK and nerr(mesh.from_dev(vv), v1) <= 1e-10
+    for bad in (96, 576, 192 | 0x10000):
+        with pytest.raises(ebbx.EbbxError) as e:
+            mesh.fem.set_strategy(ebbx.STRAT_BLOCK, bad)
+        assert e.value.code == ebbx.E_ARG
+    assert mesh.fem.get_strategy() == (ebbx.STRAT_BLOCK, blk)
+    mesh.fem.close()
+
+
 def test_step_large_mesh():
     """81^3 cube (3,188,646 tets, 551,368 vertices: more than 2048 vertex chunks, so the solver
     reduces its dot products with one workgroup per mesh instead of in every workgroup):
