@@ -348,9 +348,9 @@ def bench_one_by_one(stream, meshes, E, nu):
     return res
 
 
-def bench_adjoint(stream, plain_step_rate):
-    """48^3 cube, neo-Hookean FP64, per-tet log-normal E: 20 implicit steps (CG to 1e-10)
-    forward, then dL/dE and dL/dd0 of ||x_T - target||^2 with checkpoints every 5 steps."""
+def bench_adjoint(stream, plain_step_rate, morton=True):
+    """48^3 cube, neo-Hookean FP64, per-tet log-normal E, Morton order: 20 implicit steps (CG to
+    1e-10) forward, then dL/dE and dL/dd0 of ||x_T - target||^2 with checkpoints every 5 steps."""
     import torch
 
     from paper_1506_07577_amd import adjoint, ebbx
@@ -358,11 +358,11 @@ def bench_adjoint(stream, plain_step_rate):
     m = mg.kuhn_cube(48)
     E_tet, target, _ = mg.adjoint_recipe(m, seed=2)
     mesh = ebbx.FemMesh(m.X, m.tets, m.pinned, model=ebbx.NH, elem_prec=ebbx.F64, E=1e5, nu=0.3, E_tet=E_tet,
-                        strategy=ebbx.STRAT_BLOCK)
+                        strategy=ebbx.STRAT_BLOCK, morton=morton)
     sim = adjoint.Simulation(fem=mesh.fem, steps=20, dt=1e-3, tol=1e-10, maxit=2000, checkpoint_every=5)
     X = mesh.to_dev(m.X)
     tgt = mesh.to_dev(target)
-    Et = torch.as_tensor(E_tet, dtype=torch.float64).cuda()
+    Et = mesh.tet_to_dev(E_tet)
 
     def run():
         d0 = torch.zeros(3, mesh.nv, dtype=torch.float64, device="cuda", requires_grad=True)
