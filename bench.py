@@ -218,7 +218,7 @@ def bench_autotune(stream, n):
     return out
 
 
-def bench_batch(stream, plain_rate):
+def bench_batch(stream, plain_rate, plain_loop_rate=None):
     """256 Kuhn cubes (sides 8..40), neo-Hookean, FP32 elements, per-mesh E and nu, each mesh in
     lattice order, one implicit step of every mesh with per-mesh CG to 1e-8 (maxit 1000)."""
     import torch
@@ -258,6 +258,19 @@ def bench_batch(stream, plain_rate):
     ms = min(times)
     useful = float(np.sum(nts * iters))
     rate = useful / (ms * 1e-3)
+
+    # the same step with no CG iteration (force, K v, diagonal, right-hand side, state copies)
+    def step0():
+        bm.batch.implicit_step(d, v, 1e-3, tol=1e-8, maxit=0, stats=stats, stream=stream)
+
+    reset()
+    step0()
+    pre = []
+    for _ in range(3):
+        reset()
+        pre += time_events(step0, stream, 1)
+    ms_pre = min(pre)
+    loop_rate = useful / ((ms - ms_pre) * 1e-3)
     one = bench_one_by_one(stream, meshes[::8], E[::8], nu[::8])
     return {"meshes": bm.nm, "tets": bm.nt, "verts": bm.nv, "setup_s": round(setup, 1),
             "step_ms": round(ms, 3), "cg_iters_min": int(iters.min()), "cg_iters_max": int(iters.max()),
@@ -266,6 +279,9 @@ def bench_batch(stream, plain_rate):
             "max_rel_res": max(s.rel_res for s in st),
             "tet_cg_iters_per_s": round(rate, 1),
             "vs_plain_tet_cg_iters_per_s": round(rate / plain_rate, 4) if plain_rate else None,
+            "preamble_ms": round(ms_pre, 3),
+            "loop_tet_cg_iters_per_s": round(loop_rate, 1),
+            "loop_vs_plain_loop": round(loop_rate / plain_loop_rate, 4) if plain_loop_rate else None,
             "one_by_one": one,
             "vs_one_by_one_tet_cg_iters_per_s": round(rate / one["tet_cg_iters_per_s"], 3),
             "autotune": {k: v for k, v in tuned.items() if k != "chosen_raw"}}
@@ -740,10 +756,10 @@ def main():
     if not args.no_step:
         # one implicit step, 100 CG iterations, tol = 0 (fixed count), captured graph;
         # then the same step with Rayleigh damping (alpha = 2.5 / s, beta = 4e-3 s)
-        def time_step(alpha, beta):
+        def time_step(alpha, beta, maxit=w.maxit):
             dd = d.clone()
             vv = torch.zeros_like(d)
-            fem.implicit_step(dd, vv, w.dt, tol=0.0, maxit=w.maxit, alpha=alpha, beta=beta)   # capture + warm-up
+            fem.implicit_step(dd, vv, w.dt, tol=0.0, maxit=maxit, alpha=alpha, beta=beta)   # capture + warm-up
             torch.cuda.synchronize()
             times = []
             st = None
@@ -752,7 +768,7 @@ def main():
                 vv.zero_()
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                st = fem.implicit_step(dd, vv, w.dt, tol=0.0, maxit=w.maxit, stream=stream, alpha=alpha, beta=beta)
+                st = fem.implicit_step(dd, vv, w.dt, tol=0.0, maxit=maxit, stream=stream, alpha=alpha, beta=beta)
                 e1.record(stream)
                 torch.cuda.synchronize()
                 times.append(e0.elapsed_time(e1))
@@ -761,6 +777,10 @@ def main():
         t_step, s = time_step(0.0, 0.0)
         plain_rate = nt * s.iters / (t_step * 1e-3)
         plain_step_rate = nt / (t_step * 1e-3)
+        # the same step with no CG iteration: the force, K v and diagonal passes, the right-hand
+        # side and the state copies, so that the CG loop's own rate can be compared with a batch's
+        t_pre, _s0 = time_step(0.0, 0.0, maxit=0)
+        plain_loop_rate = nt * s.iters / ((t_step - t_pre) * 1e-3)
         # per CG iteration: the K p element map (same bytes as a K u call) plus the vector
         # kernels (q = A p: y, p, mass, pinned in, q out; update: x, p, r, q, diag in, x, r, z
         # out; p = z + beta p: z, p in, p out)
@@ -771,13 +791,15 @@ def main():
                                   "cg_iter_hbm_frac": round(cg_bytes / (t_step * 1e-3 / max(s.iters, 1)) / 1e9
                                                             / HBM_PEAK_GBS, 4),
                                   "tet_cg_iters_per_s": round(plain_rate, 1),
+                                  "preamble_ms": round(t_pre, 3),
+                                  "loop_tet_cg_iters_per_s": round(plain_loop_rate, 1),
                                   "rel_res": s.rel_res, "status": s.status}
         t_damp, sd = time_step(2.5, 4e-3)
         extra["implicit_step"]["damped"] = {"alpha": 2.5, "beta": 4e-3, "ms": round(t_damp, 3),
                                             "cg_iters": sd.iters, "rel_res": sd.rel_res, "status": sd.status}
         log(f"implicit step {t_step:.3f} ms, damped {t_damp:.3f} ms")
     else:
-        plain_rate = plain_step_rate = None
+        plain_rate = plain_step_rate = plain_loop_rate = None
     if not args.no_assembled:
         # the stiffness assembled on the edges relation (Vega's representation): one-time edge
         # build, assembly of K(d), and the block-CSR product against the matrix-free K u call
@@ -826,7 +848,7 @@ def main():
         extra["autotune"] = bench_autotune(stream, args.n)
         log(f"autotune: {extra['autotune']['chosen']} in {extra['autotune']['tune_s']} s")
     if not args.no_batch:
-        extra["batched"] = bench_batch(stream, plain_rate)
+        extra["batched"] = bench_batch(stream, plain_rate, plain_loop_rate)
         log(f"batched step {extra['batched']['step_ms']} ms")
     if not args.no_adjoint:
         extra["adjoint"] = bench_adjoint(stream, plain_step_rate)
