@@ -189,7 +189,9 @@ __device__ __forceinline__ void block_body(const ElemArgs &a, uint32_t blk, uint
     if (XF)
 #pragma unroll
         for (int k = 0; k < 3; ++k) xf[k] = a.xf[k] + (size_t)blk * S;
-    T *s_h = (T *)(s_x + (XB ? 3 * S : 0));   // rows (moved to the LDS start when REUSE)
+    // rows (moved to the LDS start when REUSE); after the FP32 rest positions they start at a
+    // multiple of 4 floats
+    T *s_h = XF ? (T *)(s_xf + ((3 * S + 3) & ~3u)) : (T *)(s_x + (XB ? 3 * S : 0));
     double *s_acc = (double *)s_h;
 
     // this thread's first block vertex
@@ -781,8 +783,12 @@ static void set_vec(const double *(&dst)[3], const double *p, uint32_t nv) {
 
 size_t block_shmem(const ebbx_fem_s *F, ElemOp op) {
     const int nq = op == OP_TMUL ? 3 : op == OP_KMUL ? 2 : 1;
-    const int nx = F->blk_w == 1 ? 1 : 0;   // rest positions staged (blocks of <= 256 vertices)
-    const size_t stage = (size_t)3 * (nq + nx) * F->blk_maxv * sizeof(double);
+    // rest positions staged on blocks of <= 256 vertices: FP32 block-local offsets for FP32
+    // elements (3 columns, padded to a multiple of 4 floats), else FP64
+    const size_t nx = F->blk_w != 1 ? 0
+                      : F->prec == EBBX_F32 ? (((size_t)3 * F->blk_maxv + 3) & ~(size_t)3) * sizeof(float)
+                                            : (size_t)3 * F->blk_maxv * sizeof(double);
+    const size_t stage = (size_t)3 * nq * F->blk_maxv * sizeof(double) + nx;
     if (F->blk_red == 1) return stage + (size_t)3 * F->blk_maxv * sizeof(double);
     if (F->esize == 8) return std::max(stage, (size_t)12 * F->blk_tets * F->esize);   // rows reuse the staging
     return stage + (size_t)12 * F->blk_tets * F->esize;
