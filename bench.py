@@ -835,8 +835,8 @@ def main():
             "spmv_over_matrix_free": round(sp_ms / tk_med, 3),
             "spmv_algorithmic_bytes": sp_bytes,
             "spmv_hbm_frac": round(sp_bytes / (sp_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "block_bytes": ne * 9 * esz, "scratch_bytes": nt * 144 * 8,
-            "note": "cold calls (1 GiB flush before each); blocks at the element precision, FP64 sums"}
+            "block_bytes": ne * 9 * esz, "scratch_bytes": nt * 144 * esz,
+            "note": "cold calls (1 GiB flush before each); per-tet records and edge blocks at the element precision, FP64 sums"}
         log(f"assembled: build {build_s:.2f} s, assemble {statistics.median(ta):.3f} ms, spmv {1e3 * sp_ms:.1f} us")
     if not args.no_springs:
         extra["springs"] = bench_springs(stream, flush_bytes)

@@ -10,10 +10,12 @@
 //  - k_elem_matrix: one thread per tet computes the tet's 12 x 12 stiffness in
 //    FP64, column by column (a unit displacement of corner b along axis k gives
 //    dF = e_k (x) grad N_b), with the element maps' own dP, and writes its
-//    sixteen 3x3 corner blocks to a per-tet record, one block column at a time
-//    through LDS so that the workgroup writes each tet's four blocks of that
-//    column (288 contiguous bytes) together (per-thread scattered stores of the
-//    record wrote 2.45x its bytes);
+//    sixteen 3x3 corner blocks, rounded to the element precision, to a per-tet
+//    record (the same rounding as the matrix-free map's per-tet corner results,
+//    which are also summed in FP64), one block column at a time through LDS so
+//    that the workgroup writes each tet's four blocks of that column (36
+//    contiguous values) together (per-thread scattered stores of the record
+//    wrote 2.45x its bytes);
 //  - k_edge_gather: one thread per edge sums the corner blocks of the tets
 //    holding both of its vertices in ascending tet order (deterministic) and
 //    stores the edge block at the element precision, nine columns (SoA);
@@ -39,7 +41,8 @@ struct AsmArgs {
     const void *mu_t, *lam_t;
     double mu, lam;
     const double *d[3];
-    double *ke;                  // (nt, 16, 9): block (a, b) of tet t at ke[(16 t + 4 a + b) * 9]
+    void *ke;                    // (nt, 16, 9) at the element precision: block (a, b) of tet t at
+                                 // ke[(16 t + 4 b + a) * 9]
     unsigned long long *n_inv;
     const int32_t *tmesh;
 };
@@ -47,8 +50,9 @@ struct AsmArgs {
 constexpr int EM_THREADS = 128;   // tets per workgroup of the element-matrix kernel
 constexpr int EM_STRIDE = 37;     // LDS doubles per tet for one block column (36, padded)
 
-// Per-tet record: 144 doubles, block (a, b) (rows of corner a, columns of corner b) at
-// (4 b + a) * 9, row-major; so the four blocks of one column b are 36 contiguous doubles.
+// Per-tet record: 144 values at the element precision, block (a, b) (rows of corner a, columns
+// of corner b) at (4 b + a) * 9, row-major; so the four blocks of one column b are 36
+// contiguous values.
 template <class T, int MODEL>
 __global__ __launch_bounds__(EM_THREADS) void k_elem_matrix(AsmArgs a) {
     __shared__ double s_col[EM_THREADS * EM_STRIDE];
@@ -103,7 +107,7 @@ __global__ __launch_bounds__(EM_THREADS) void k_elem_matrix(AsmArgs a) {
         __syncthreads();
         for (uint32_t e = threadIdx.x; e < nloc * 36u; e += EM_THREADS) {
             const uint32_t i = e / 36u, o = e - 36u * i;
-            a.ke[(size_t)(t0 + i) * 144 + 36u * cb + o] = s_col[i * EM_STRIDE + o];
+            ((T *)a.ke)[(size_t)(t0 + i) * 144 + 36u * cb + o] = (T)s_col[i * EM_STRIDE + o];
         }
         __syncthreads();
     }
@@ -112,9 +116,11 @@ __global__ __launch_bounds__(EM_THREADS) void k_elem_matrix(AsmArgs a) {
 
 // blocks[q][e] = sum over the edge's (tet, a, b) entries, in tet order, of ke block q
 template <class T>
-__global__ __launch_bounds__(256) void k_edge_gather(const double *ke, const int32_t *gptr, const uint32_t *gent,
+__global__ __launch_bounds__(256) void k_edge_gather(const T *ke, const int32_t *gptr, const uint32_t *gent,
                                                      uint32_t ne, T *blocks) {
-    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD x sums one contiguous range of edges (tails in mesh order), so the records of a tet,
+    // which its four corners' edges all read, come into one L2 rather than up to four
+    const uint32_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (e >= ne) return;
     double s[9];
 #pragma unroll
@@ -122,9 +128,9 @@ __global__ __launch_bounds__(256) void k_edge_gather(const double *ke, const int
     const int32_t j0 = gptr[e], j1 = gptr[e + 1];
     for (int32_t j = j0; j < j1; ++j) {
         const uint32_t c = gent[j];   // 16 t + 4 a + b: block (a, b) of tet t
-        const double *blk = ke + (size_t)(c >> 4) * 144 + (4u * (c & 3u) + ((c >> 2) & 3u)) * 9;
+        const T *blk = ke + (size_t)(c >> 4) * 144 + (4u * (c & 3u) + ((c >> 2) & 3u)) * 9;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) s[q] += blk[q];
+        for (int q = 0; q < 9; ++q) s[q] += (double)blk[q];
     }
 #pragma unroll
     for (int q = 0; q < 9; ++q) blocks[(size_t)q * ne + e] = (T)s[q];
@@ -141,7 +147,8 @@ template <class T> struct BsrArgs {
 
 template <class T>
 __global__ __launch_bounds__(256) void k_bsr_spmv(BsrArgs<T> a) {
-    const uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / SPMV_LANES;
+    // XCD x takes one contiguous range of rows, whose neighbours' u it shares in its L2
+    const uint32_t g = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / SPMV_LANES;
     const uint32_t lane = threadIdx.x % SPMV_LANES;
     const uint32_t i = g < a.nv ? g : a.nv - 1;   // whole groups stay in the shuffles
     const int32_t e0 = a.row[i], e1 = g < a.nv ? a.row[i + 1] : e0;
@@ -246,7 +253,7 @@ template <class T> void launch_assemble(ebbx_fem_s *F, const double *d, hipStrea
         a.mu = F->mu;
         a.lam = F->lam;
         for (int k = 0; k < 3; ++k) a.d[k] = d + (size_t)k * nv;
-        a.ke = F->e_ke.as<double>();
+        a.ke = F->e_ke.get();
         a.n_inv = F->status.as<unsigned long long>();
         a.tmesh = F->tmesh;
         if (F->model == EBBX_STVK)
@@ -258,7 +265,7 @@ template <class T> void launch_assemble(ebbx_fem_s *F, const double *d, hipStrea
     const int64_t ne = F->n_edges;
     if (ne > 0) {
         hipLaunchKernelGGL((k_edge_gather<T>), dim3(grid_of(ne, 256)), dim3(256), 0, s,
-                           (const double *)F->e_ke.get(), F->e_gptr.as<int32_t>(), F->e_gent.as<uint32_t>(),
+                           (const T *)F->e_ke.get(), F->e_gptr.as<int32_t>(), F->e_gent.as<uint32_t>(),
                            (uint32_t)ne, F->e_blocks.as<T>());
         HIPCHK(hipGetLastError());
     }
@@ -286,7 +293,7 @@ void assemble_stiffness(ebbx_fem_s *F, const double *d, hipStream_t s) {
     build_edges(F, s);
     // the blocks and the per-tet scratch, on the first assembly
     const size_t blk_bytes = std::max<size_t>((size_t)9 * F->n_edges * F->esize, 8);
-    const size_t ke_bytes = std::max<size_t>((size_t)F->nt * 144 * sizeof(double), 8);
+    const size_t ke_bytes = std::max<size_t>((size_t)F->nt * 144 * F->esize, 8);
     if (F->e_blocks.bytes() != blk_bytes) F->e_blocks.reset(blk_bytes, s);
     if (F->e_ke.bytes() != ke_bytes) F->e_ke.reset(ke_bytes, s);
     if (F->prec == EBBX_F32) launch_assemble<float>(F, d, s);
