@@ -153,7 +153,9 @@ template <int L, int U>
 __global__ __launch_bounds__(256) void k_spring_forces(const int32_t *row, const int32_t *head, const double *rest,
                                                        double K, const double *q, double *f, uint32_t nv,
                                                        int accumulate) {
-    const uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    // XCD x takes one contiguous range of vertices (Morton-ordered), whose neighbours' positions
+    // it then mostly finds in its own L2
+    const uint32_t g = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / L;
     const uint32_t lane = threadIdx.x % L;
     const uint32_t v = g < nv ? g : nv - 1;   // whole groups stay in the shuffles
     const int32_t e0 = row[v], e1 = g < nv ? row[v + 1] : e0;
@@ -174,7 +176,9 @@ template <int L, int U>
 __global__ __launch_bounds__(256) void k_spring_step(const int32_t *row, const int32_t *head, const double *rest,
                                                      double K, const double *mass, double dt, const double *q,
                                                      double *q_out, double *qd, double *f, int take_f, uint32_t nv) {
-    const uint32_t g = (blockIdx.x * blockDim.x + threadIdx.x) / L;
+    // XCD x takes one contiguous range of vertices (Morton-ordered), whose neighbours' positions
+    // it then mostly finds in its own L2
+    const uint32_t g = (xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) / L;
     const uint32_t lane = threadIdx.x % L;
     const uint32_t v = g < nv ? g : nv - 1;
     const int32_t e0 = row[v], e1 = g < nv ? row[v + 1] : e0;
