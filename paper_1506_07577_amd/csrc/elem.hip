@@ -436,6 +436,152 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
 }
 
+// The run sum of one block vertex for output column set `out` (owned) or halo slot `hq`
+// (shared), as reduce_slot, overwriting (the step preamble does not accumulate).
+template <class T>
+__device__ __forceinline__ void reduce_pre(const T *s_h, uint32_t LB, uint32_t gv, double *const *out, double *hq,
+                                           int32_t j0, int32_t j1) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
+    for (int32_t j = j0; j < j1; ++j) {
+        a0 += (double)s_h[j];
+        a1 += (double)s_h[LB + j];
+        a2 += (double)s_h[2 * LB + j];
+    }
+    if (!hq) {
+        stc<double>(out[0], gv, a0);
+        stc<double>(out[1], gv, a1);
+        stc<double>(out[2], gv, a2);
+    } else {
+        hq[0] = a0;
+        hq[1] = a1;
+        hq[2] = a2;
+    }
+}
+
+// The implicit step's preamble for one tet block: the forces f(d), the product K(d) u and the
+// raw stiffness diagonal.  The block's d and u (and rest positions) are staged once, and each
+// tet's rest shape and gradients are formed once; the three per-corner results then pass through
+// the incidence-order rows one after another (rows, barrier, run sums, barrier), so each output
+// is summed exactly as its own element map would sum it.  Owned vertices store f, K u and the
+// diagonal; a shared vertex writes its three partials to one 9-wide halo entry.
+template <class T, int MODEL, int W>
+__device__ __forceinline__ void block_body_pre(const ElemArgs &a, uint32_t blk, uint32_t tid) {
+    extern __shared__ uint4 s_dyn4[];
+    const uint32_t nt = a.nt, BT = blockDim.x, LB = 4 * BT;
+    const uint32_t S = a.blk_stride;
+    const int32_t *bverts = a.blk_verts + (size_t)blk * S;
+    const int32_t *bhpos = a.blk_hpos + (size_t)blk * S;
+    const uint16_t *brow = a.blk_row + (size_t)blk * (S + 1);
+    const uint32_t t = blk * BT + tid;
+    const bool in = t < nt;
+    // the LDS layout of the stiffness product's block kernel (d, u, then the rest positions)
+    constexpr bool XB = W == 1;
+    constexpr bool XF = XB && sizeof(T) == 4;
+    constexpr bool REUSE = sizeof(T) == 8;   // FP64 rows overwrite the staging
+    double *s_d = (double *)s_dyn4;
+    double *s_u = s_d + 3 * S;
+    double *s_x = s_u + 3 * S;
+    float *s_xf = (float *)s_x;
+    T *s_h = REUSE ? (T *)s_dyn4 : XF ? (T *)(s_xf + ((3 * S + 3) & ~3u)) : (T *)(s_x + (XB ? 3 * S : 0));
+
+    const int32_t gvs0 = tid < S ? bverts[tid] : -1;
+    const bool has = gvs0 >= 0;
+    const uint32_t gv0 = has ? (uint32_t)gvs0 : 0u;
+    int32_t hp0 = -1, j00 = 0, j10 = 0;
+    if (has) {
+        hp0 = bhpos[tid];
+        j00 = brow[tid];
+        j10 = brow[tid + 1];
+    }
+    T b[9], V0 = T(1), mu = T(0), lam = T(0);
+    uint32_t sl[4] = {0, 0, 0, 0}, pw[2] = {0, 0};
+    if (in) {
+        if (!XB) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) b[k] = ldc<T>(a.B[k], t);
+            V0 = tet_V0(b);
+        }
+        if (a.mu_t) {
+            mu = ldc<T>(a.mu_t, t);
+            lam = ldc<T>(a.lam_t, t);
+        } else {
+            mu = (T)a.mu;
+            lam = (T)a.lam;
+        }
+        unpack_slots<W>(a, t, sl);
+        pw[0] = ldc<uint32_t>(a.blk_pos[0], t);
+        pw[1] = ldc<uint32_t>(a.blk_pos[1], t);
+    }
+    const float *xf[3] = {nullptr, nullptr, nullptr};
+    if (XF)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) xf[k] = a.xf[k] + (size_t)blk * S;
+    for (uint32_t i = tid; i < S; i += BT) {
+        const int32_t gvs = i == tid ? gvs0 : bverts[i];
+        if (gvs < 0) continue;
+        const uint32_t gv = (uint32_t)gvs;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            s_d[k * S + i] = ldc<double>(a.d[k], gv);
+            s_u[k * S + i] = ldc<double>(a.u[k], gv);
+            if (XF) s_xf[k * S + i] = xf[k][i];
+            else if (XB) s_x[k * S + i] = ldc<double>(a.X[k], gv);
+        }
+    }
+    __syncthreads();
+    T G[9], dF[9];
+    if (in) {
+        if constexpr (XF) rest_B_local(s_xf, S, sl, b, V0);
+        else if (XB) rest_B(s_x, S, sl, b, V0);
+        staged_grad(s_d, S, sl, b, G);
+        staged_grad(s_u, S, sl, b, dF);
+    }
+    const uint32_t p[4] = {pw[0] & 0xffffu, pw[0] >> 16, pw[1] & 0xffffu, pw[1] >> 16};
+    // unrolled: each phase keeps only the registers it needs (78 VGPRs for the FP32 neo-Hookean
+    // pass against 102 with one loop body)
+#pragma unroll
+    for (int ph = 0; ph < 3; ++ph) {
+        __syncthreads();   // the staging (REUSE) or the previous phase's rows are no longer read
+        if (in) {
+            T h[12];
+            if (ph == 0) {
+                T P[9];
+                const bool ok = stress_scaled<T, MODEL>(mu, lam, V0, G, P);
+                corner_out(P, b, h);
+                if (MODEL == EBBX_NH && !ok) atomicAdd(a.n_inv + (a.tmesh ? a.tmesh[t] : 0), 1ull);
+            } else if (ph == 1) {
+                T dP[9];
+                dstress_scaled<T, MODEL>(mu, lam, V0, G, dF, dP);
+                corner_out(dP, b, h);
+            } else {
+                diag12<T, MODEL>(mu, lam, G, b, V0, h);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                s_h[p[c]] = h[3 * c];
+                s_h[LB + p[c]] = h[3 * c + 1];
+                s_h[2 * LB + p[c]] = h[3 * c + 2];
+            }
+        }
+        __syncthreads();
+        double *const *out = a.pre_out[ph];
+        if (has) reduce_pre<T>(s_h, LB, gv0, out, hp0 < 0 ? nullptr : a.halo9 + 9 * (size_t)hp0 + 3 * ph, j00, j10);
+        for (uint32_t i = tid + BT; i < S; i += BT) {
+            const int32_t gvs = bverts[i];
+            if (gvs < 0) continue;
+            const int32_t hp = bhpos[i];
+            reduce_pre<T>(s_h, LB, (uint32_t)gvs, out, hp < 0 ? nullptr : a.halo9 + 9 * (size_t)hp + 3 * ph, brow[i],
+                          brow[i + 1]);
+        }
+    }
+}
+
+template <class T, int MODEL, int W>
+__global__ __launch_bounds__(512) void k_block_pre(ElemArgs a) {
+    block_body_pre<T, MODEL, W>(a, xcd_block(blockIdx.x, a.nblk, a.xcd_run_log2), threadIdx.x);
+}
+
 // OWNER strategy: workgroup = one block of owned vertices.  The block stages
 // the fields of its vertices (owned, then ghosts) in LDS, evaluates every tet
 // listed for it, writes the rows of owned corners to their positions in the
@@ -1215,6 +1361,63 @@ HaloView elem_halo_view(const ebbx_fem_s *F) {
     h.halo = F->halo.as<double>();
     h.nc = F->sh_nc;
     return h;
+}
+
+bool elem_pre_ok(const ebbx_fem_s *F) {
+    return F->strategy == EBBX_STRAT_BLOCK && F->blk_red == 0 && F->blk_tpt == 1 && F->halo_level == 0 &&
+           F->nt > 0 && F->nv > 0;
+}
+
+void elem_pre_prepare(ebbx_fem_s *F, hipStream_t s) {
+    const size_t bytes = std::max<size_t>((size_t)F->halo_n * 9 * sizeof(double), 8);
+    if (F->halo9.bytes() != bytes) F->halo9.reset(bytes, s);
+}
+
+HaloView elem_pre_halo(const ebbx_fem_s *F) {
+    HaloView h = elem_halo_view(F);
+    if (h.row) h.halo = F->halo9.as<double>();
+    return h;
+}
+
+void elem_launch_pre(ebbx_fem_s *F, const double *d, const double *u, double *f, double *y, double *diag,
+                     hipStream_t s) {
+    if (!elem_pre_ok(F)) fail(EBBX_E_STATE, "the fused step preamble needs the block strategy (one tet per thread)");
+    const size_t need = (size_t)F->halo_n * 9 * sizeof(double);
+    if (F->halo9.bytes() < std::max<size_t>(need, 8)) fail(EBBX_E_STATE, "the fused step preamble's halo is not allocated");
+    const int64_t nv = F->nv;
+    ElemArgs a = base_args(F);
+    set_vec(a.d, d, (uint32_t)nv);
+    set_vec(a.u, u, (uint32_t)nv);
+    double *outs[3] = {f, y, diag};
+    for (int ph = 0; ph < 3; ++ph)
+        for (int k = 0; k < 3; ++k) a.pre_out[ph][k] = outs[ph] + (size_t)k * nv;
+    a.halo9 = F->halo9.as<double>();
+    const size_t shmem = block_shmem(F, OP_KMUL);   // d and u staged, one row set
+    if (shmem > lds_limit())
+        fail(EBBX_E_STATE, "block strategy needs %zu bytes of LDS per block (%d vertices); reorder the mesh "
+             "(Morton) or use smaller blocks", shmem, F->blk_maxv);
+    const int threads = F->blk_tets;
+    if (threads > 512) fail(EBBX_E_ARG, "block strategy: at most 512 tets per block with one tet per thread");
+    const dim3 g((unsigned)F->nblk), b((unsigned)threads);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, g, b, shmem, s, a); };
+    if (F->prec == EBBX_F32) {
+        if (F->model == EBBX_STVK) {
+            if (F->blk_w == 1) go(k_block_pre<float, EBBX_STVK, 1>);
+            else go(k_block_pre<float, EBBX_STVK, 2>);
+        } else {
+            if (F->blk_w == 1) go(k_block_pre<float, EBBX_NH, 1>);
+            else go(k_block_pre<float, EBBX_NH, 2>);
+        }
+    } else {
+        if (F->model == EBBX_STVK) {
+            if (F->blk_w == 1) go(k_block_pre<double, EBBX_STVK, 1>);
+            else go(k_block_pre<double, EBBX_STVK, 2>);
+        } else {
+            if (F->blk_w == 1) go(k_block_pre<double, EBBX_NH, 1>);
+            else go(k_block_pre<double, EBBX_NH, 2>);
+        }
+    }
+    HIPCHK(hipGetLastError());
 }
 
 // ---- block tables -----------------------------------------------------------------------

@@ -95,6 +95,10 @@ struct ElemArgs {
                                 // all finished returns at once (block strategies)
     const int32_t *act;         // nullable: the active list of a batched solve (k_block_list)
     int32_t act_nm;             // meshes of that batch (the list's array stride)
+    // the fused step preamble (k_block_pre): f, K u and the stiffness diagonal, each into three
+    // columns; shared vertices' partials go to halo9, 9 per entry (f, then K u, then diagonal)
+    double *pre_out[3][3];
+    double *halo9;
 };
 
 // Launch the element map `op` with the FEM's current strategy; result into
@@ -131,6 +135,16 @@ void elem_egrad(ebbx_fem_s *F, const double *d, const double *v, const double *w
                 double *E_bar, hipStream_t s);
 // Recompute the per-tet Lame parameters from per-tet (or uniform) E and nu.
 void elem_set_material(ebbx_fem_s *F, const double *E_tet, const double *nu_tet, double E, double nu, hipStream_t s);
+// The implicit step's three element maps at the state d in one pass of the block strategy
+// (BLOCK, one tet per thread, incidence-order sums; elem_pre_ok): f(d) into f, K(d) u into y and
+// the raw stiffness diagonal into diag, with the same per-tet arithmetic and summation order as
+// the three separate maps.  Shared vertices stay in the 9-wide halo of elem_pre_halo for the
+// consumer (elem_pre_prepare allocates it; call it outside stream capture).
+bool elem_pre_ok(const ebbx_fem_s *F);
+void elem_pre_prepare(ebbx_fem_s *F, hipStream_t s);
+void elem_launch_pre(ebbx_fem_s *F, const double *d, const double *u, double *f, double *y, double *diag,
+                     hipStream_t s);
+HaloView elem_pre_halo(const ebbx_fem_s *F);
 // Total energy into out_dev[0].
 void elem_energy(ebbx_fem_s *F, const double *d, double *out_dev, hipStream_t s);
 // Rest-shape precompute; returns the number of degenerate tets.
@@ -231,6 +245,7 @@ struct ebbx_fem_s {
     ebbx::DevBuf blk_xf;   // block-local FP32 rest positions (FP32 elements, blocks of <= 256 vertices)
     ebbx::DevBuf blk_vptr, blk_verts, blk_lptr, blk_pos, blk_hpos, blk_local, halo, sh_vert, sh_ptr, sh_pos, sh_tab,
         sh_row;
+    ebbx::DevBuf halo9;        // the fused step preamble's halo (9 values per entry)
     int32_t sh_nc = 0;         // int4 chunks per row of sh_tab (0: use the CSR form)
     bool blocks_built = false;
     int32_t halo_level = -1;   // the halo and shared-vertex tables are of: 0 blocks, g >= 1 super-blocks of

@@ -243,9 +243,44 @@ __global__ void k_step_begin(CGState *st, int nm, SolveCtl *ctl, unsigned long l
 // mode 0 (step): b = dt (f + M g - alpha M v_n + (dt + beta) y), with f = f(d_n)
 // and y = K(d_n) v_n;
 // mode 1 (adjoint solve): b = f, the right-hand side placed in f beforehand.
+// f, K v and the stiffness diagonal of vertex v as the fused step preamble left them: a shared
+// vertex sums its 9-wide halo entries in unit order, as the halo pass of each map would.
+__device__ __forceinline__ void finished_pre(const HaloView &h, const StepVec &w, int64_t nv, int64_t v,
+                                             double (&o)[9]) {
+    const int32_t r = h.row ? h.row[v] : -1;
+    if (r < 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            o[k] = w.f[k * nv + v];
+            o[3 + k] = w.y[k * nv + v];
+            o[6 + k] = w.diag[k * nv + v];
+        }
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 9; ++j) o[j] = 0.0;
+    auto add = [&](int32_t pos) {
+        const double *hq = h.halo + 9 * (size_t)pos;
+#pragma unroll
+        for (int j = 0; j < 9; ++j) o[j] += hq[j];
+    };
+    if (h.nc > 0) {
+        for (int c = 0; c < h.nc; ++c) {
+            const int4 q = h.tab[(size_t)r * h.nc + c];
+            const int32_t p4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (p4[k] >= 0) add(p4[k]);
+        }
+    } else {
+        for (int32_t j = h.ptr[r]; j < h.ptr[r + 1]; ++j) add(h.pos[j]);
+    }
+}
+
+// pre (nullable row): the step's f, K v and diagonal come from the fused preamble and its halo
 __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
                                                  double dt, double gx, double gy, double gz, double alpha, double beta,
-                                                 int precond, int mode, Chunks ch, double *part) {
+                                                 int precond, int mode, Chunks ch, double *part, HaloView pre) {
     const double cm = 1.0 + dt * alpha, ck = dt * dt + dt * beta;
     __shared__ double s4[4];
     const int c = chunk_of(ch);
@@ -255,11 +290,14 @@ __global__ __launch_bounds__(VT) void k_step_rhs(StepVec w, const double *mass, 
         const double m = mass[v];
         const bool pin = pinned[v] != 0;
         const double g[3] = {gx, gy, gz};
+        double fyd[9];
+        if (pre.row) finished_pre(pre, w, nv, v, fyd);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
-            const double b = mode ? w.f[i] : dt * (w.f[i] + m * g[k] - alpha * m * w.vn[i] + (dt + beta) * w.y[i]);
-            const double dg = pin ? 1.0 : (precond ? cm * m - ck * w.diag[i] : 1.0);
+            const double fk = pre.row ? fyd[k] : w.f[i], yk = pre.row ? fyd[3 + k] : w.y[i];
+            const double b = mode ? w.f[i] : dt * (fk + m * g[k] - alpha * m * w.vn[i] + (dt + beta) * yk);
+            const double dg = pin ? 1.0 : (precond ? cm * m - ck * (pre.row ? fyd[6 + k] : w.diag[i]) : 1.0);
             const double r = pin ? 0.0 : b;
             const double z = r / dg;
             w.diag[i] = dg;
@@ -719,19 +757,34 @@ struct SolveBufs {
     const int64_t *tptr;    // batches: the meshes' tet offsets
 };
 
+// Whether the step preamble of `mode` runs the fused element pass (the step, with the Jacobi
+// preconditioner, under the block strategy).
+bool pre_fused(const ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
+    return mode == 0 && p.precond == EBBX_PRECOND_JACOBI && elem_pre_ok(F);
+}
+
 // The preamble of `mode` (0: step, 1: adjoint solve) onto stream cs: state reset, (step)
 // forces and K v, the Jacobi diagonal, the right-hand side and the initial residual.
 void launch_preamble(ebbx_fem_s *F, const ebbx_step_params &p, int mode, const SolveBufs &b, hipStream_t cs) {
     const int64_t nv = F->nv;
     unsigned long long *n_inv = F->status.as<unsigned long long>();
     hipLaunchKernelGGL(k_step_begin, dim3((b.nm + VT - 1) / VT), dim3(VT), 0, cs, b.st, b.nm, b.ctl, n_inv);
-    if (mode == 0) {
-        elem_launch(F, OP_FORCE, b.w.dn, nullptr, b.w.f, 0, cs);
-        elem_launch(F, OP_KMUL, b.w.dn, b.w.vn, b.w.y, 0, cs);
+    // the block strategy evaluates the step's force, K v and diagonal in one fused pass whose
+    // shared vertices k_step_rhs finishes; other strategies run the three maps
+    const bool fused = pre_fused(F, p, mode);
+    HaloView pre{};
+    if (fused) {
+        elem_launch_pre(F, b.w.dn, b.w.vn, b.w.f, b.w.y, b.w.diag, cs);
+        pre = elem_pre_halo(F);
+    } else {
+        if (mode == 0) {
+            elem_launch(F, OP_FORCE, b.w.dn, nullptr, b.w.f, 0, cs);
+            elem_launch(F, OP_KMUL, b.w.dn, b.w.vn, b.w.y, 0, cs);
+        }
+        if (p.precond == EBBX_PRECOND_JACOBI) elem_launch(F, OP_DIAG, b.w.dn, nullptr, b.w.diag, 0, cs);
     }
-    if (p.precond == EBBX_PRECOND_JACOBI) elem_launch(F, OP_DIAG, b.w.dn, nullptr, b.w.diag, 0, cs);
     hipLaunchKernelGGL(k_step_rhs, dim3(b.nch), dim3(VT), 0, cs, b.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
-                       nv, p.dt, p.g[0], p.g[1], p.g[2], p.alpha, p.beta, p.precond, mode, b.ch, b.part);
+                       nv, p.dt, p.g[0], p.g[1], p.g[2], p.alpha, p.beta, p.precond, mode, b.ch, b.part, pre);
     hipLaunchKernelGGL(k_step_init, dim3(b.nm), dim3(VT), 0, cs, b.st, (const double *)b.part, b.ch,
                        (const unsigned long long *)n_inv, b.ctl);
     HIPCHK(hipGetLastError());
@@ -796,6 +849,7 @@ void build_graphs(ebbx_fem_s *F, const ebbx_step_params &p, int mode) {
     if (S.pre[mode]) return;
     const SolveBufs b = step_bufs(F);
     hipStream_t cs = S.cap;
+    if (pre_fused(F, p, mode)) elem_pre_prepare(F, cs);   // its halo, allocated outside the capture
     capture_begin(cs);
     CaptureGuard guard(cs);
     launch_preamble(F, p, mode, b, cs);

@@ -335,6 +335,26 @@ def test_step_error_conditions():
     mesh.fem.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_step_inverted_fused_preamble(prec):
+    """The block strategy's step evaluates force, K v and diagonal in one fused pass: it counts
+    the same inverted elements as the unfused preamble (ATOMIC strategy) and leaves the state."""
+    m = _mesh_small()
+    z = np.zeros((m.nv, 3))
+    dinv = np.zeros((m.nv, 3))
+    dinv[:, 0] = -2.0 * m.X[:, 0]
+    counts = []
+    for strat in ["atomic", "block"]:
+        mesh, _ = _pair(m, 1, prec, strat, morton=(strat == "block"))
+        d, v = mesh.to_dev(dinv), mesh.to_dev(z)
+        s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-3, maxit=5))
+        assert s.status == ebbx.E_INVERTED and s.n_inverted > 0, strat
+        assert torch.count_nonzero(v).item() == 0, strat
+        counts.append(s.n_inverted)
+        mesh.fem.close()
+    assert counts[0] == counts[1]
+
+
 def test_free_fall_unpinned():
     m = mg.jitter(mg.kuhn_cube(4), 0.01, seed=0)
     mesh = ebbx.FemMesh(m.X, m.tets, None, model=1, elem_prec=ebbx.F64, E=1e5, nu=0.3)
