@@ -290,6 +290,32 @@ def test_step_small_config(strat):
     mesh.fem.close()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("model", [0, 1])
+def test_step_fused_preamble_configs(model, prec):
+    """The block strategy's fused step preamble (force, K v, diagonal in one pass) on the block
+    shapes it specialises: a scrambled 8^3 mesh (blocks of more than 256 vertices: 16-bit corner
+    slots, streamed B) with per-tet E, and the Morton-ordered mesh (8-bit slots, rest shape from
+    the staged positions), two steps each against the oracle."""
+    m0 = mg.jitter(mg.kuhn_cube(8), 0.01, seed=0)
+    m, _pv, _pt = mg.scramble(m0, seed=4)
+    E_tet = 1e5 * (1.0 + 0.5 * np.random.default_rng(5).random(m.nt))
+    tol = 1e-10 if prec == "f64" else 1e-5
+    for morton in (False, True):
+        mesh, ref = _pair(m, model, prec, "block", E_tet=E_tet, morton=morton)
+        d0 = mg.perturbed_state(m, 0.01, seed=12)
+        v0 = 0.1 * mg.direction(m, 13)
+        d, v = mesh.to_dev(d0), mesh.to_dev(v0)
+        dr, vr = d0, v0
+        for _ in range(2):
+            s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-3, tol=0.0, maxit=40))
+            dr, vr, _dv, _so = ref.implicit_step(dr, vr, 1e-3, tol=0.0, maxit=40)
+            assert s.status == 0, morton
+            assert nerr(mesh.from_dev(v), vr) <= tol, morton
+            assert nerr(mesh.from_dev(d), dr) <= tol, morton
+        mesh.fem.close()
+
+
 @pytest.mark.parametrize("precond", [0, 1])
 def test_step_tolerance_and_iterations(precond):
     m = mg.jitter(mg.kuhn_cube(6), 0.01, seed=0)
