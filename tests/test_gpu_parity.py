@@ -316,10 +316,13 @@ def test_step_fused_preamble_configs(model, prec):
         mesh.fem.close()
 
 
+@pytest.mark.parametrize("strat", ["seg", "block"])
 @pytest.mark.parametrize("precond", [0, 1])
-def test_step_tolerance_and_iterations(precond):
+def test_step_tolerance_and_iterations(precond, strat):
+    """Tolerance-terminated steps with and without the Jacobi preconditioner (the block strategy
+    fuses its preamble's element maps only with it)."""
     m = mg.jitter(mg.kuhn_cube(6), 0.01, seed=0)
-    mesh, ref = _pair(m, 1, "f64", "seg", E=1e6, nu=0.45)
+    mesh, ref = _pair(m, 1, "f64", strat, E=1e6, nu=0.45, morton=(strat == "block"))
     d0 = mg.perturbed_state(m, 0.02, seed=10)
     v0 = 0.1 * mg.direction(m, 11)
     d, v = mesh.to_dev(d0), mesh.to_dev(v0)
