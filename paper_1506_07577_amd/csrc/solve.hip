@@ -591,6 +591,107 @@ __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *s
     for (int k = 0; k < 3; ++k) w.p[k * nv + v] = z[k] + beta * p[k];
 }
 
+// One CG iteration after K p for a single mesh of at most SMALL_NV vertices, in one workgroup:
+// the passes of k_cg_Ap, k_cg_update_f and k_cg_p_f with workgroup barriers where the large
+// solve needs a launch (each dot product is one fixed-order workgroup sum).  The CG scalars live
+// in the mesh's state (r.z carried there from one iteration to the next).  A small mesh's
+// iteration is launch-bound, so two launches instead of four halve it.
+constexpr int SMALL_T = 1024;
+constexpr int64_t SMALL_NV = 4096;
+
+__device__ __forceinline__ double block_sum_small(double x, double *s16) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) s16[threadIdx.x >> 6] = x;
+    __syncthreads();
+    // the first four waves combine as block_sum does, so a mesh of at most VT vertices (one
+    // chunk, the other waves' sums zero) gets the sums of the multi-workgroup path bit for bit
+    const double a = (s16[0] + s16[1]) + (s16[2] + s16[3]);
+    double b = 0.0;
+#pragma unroll
+    for (int g = 1; g < SMALL_T / 256; ++g) b += (s16[4 * g] + s16[4 * g + 1]) + (s16[4 * g + 2] + s16[4 * g + 3]);
+    return a + b;
+}
+
+__global__ __launch_bounds__(SMALL_T) void k_cg_iter_small(StepVec w, const double *mass, const uint8_t *pinned,
+                                                           int64_t nv, double cm, double ck, CGState *st, HaloView hv,
+                                                           double tol, int maxit, SolveCtl *ctl) {
+    __shared__ double s16[SMALL_T / 64];
+    CGState &s = st[0];
+    if (s.done) return;   // uniform
+    // q = Pi (cm M p - ck K p) and p.q
+    double pq = 0.0;
+    for (int64_t v = threadIdx.x; v < nv; v += SMALL_T) {
+        const double m = mass[v];
+        const bool pin = pinned[v] != 0;
+        double y[3];
+        finished(hv, w.y, nv, v, y);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            const double p = w.p[i];
+            const double q = pin ? 0.0 : cm * m * p - ck * y[k];
+            w.q[i] = q;
+            pq += p * q;
+        }
+    }
+    pq = block_sum_small(pq, s16);
+    const double rz0 = s.rz;
+    if (!(pq > 0.0)) {   // breakdown: x and r are left alone
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            s.pq = pq;
+            s.status = EBBX_E_NOT_SPD;
+            mark_done(s, ctl, 0);
+        }
+        return;
+    }
+    const double alpha = rz0 / pq;
+    // x += alpha p; r -= alpha q; z = D^-1 r (each thread rereads only what it wrote)
+    double rz = 0.0, rr = 0.0;
+    for (int64_t v = threadIdx.x; v < nv; v += SMALL_T) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            w.x[i] += alpha * w.p[i];
+            const double rn = w.r[i] - alpha * w.q[i];
+            const double z = rn / w.diag[i];
+            w.r[i] = rn;
+            w.z[i] = z;
+            rz += rn * z;
+            rr += rn * rn;
+        }
+    }
+    rz = block_sum_small(rz, s16);
+    rr = block_sum_small(rr, s16);
+    const bool conv = sqrt(rr) <= tol * s.bnorm || rz == 0.0;
+    const double beta = rz / rz0;
+    __syncthreads();   // every thread has read the state before thread 0 updates it
+    if (threadIdx.x == 0) {
+        s.pq = pq;
+        s.alpha = alpha;
+        const int it = s.iters + 1;
+        s.iters = it;
+        s.rr = rr;
+        if (conv) {
+            s.converged = 1;
+            mark_done(s, ctl, 0);
+        } else {
+            s.beta = beta;
+            s.rz = rz;
+            if (it >= maxit) mark_done(s, ctl, 0);
+        }
+    }
+    if (conv) return;
+    for (int64_t v = threadIdx.x; v < nv; v += SMALL_T)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            w.p[i] = w.z[i] + beta * w.p[i];
+        }
+}
+
 __global__ void k_copy_in(const double *d, const double *v, double *dn, double *vn, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         dn[i] = d[i];
@@ -806,6 +907,16 @@ void launch_iterations(ebbx_fem_s *F, const ebbx_step_params &p, const SolveBufs
     // meshes, rebuilt at the start of every iteration, so finished meshes cost no workgroups
     const bool list = b.act && elem_list_ok(F, OP_KMUL);
     const int32_t *act = list ? b.act : nullptr;
+    if (b.nm == 1 && b.fused && nv <= SMALL_NV) {
+        // a small mesh: K p, then one single-workgroup kernel for the rest of the iteration
+        for (int it = 0; it < count && it < p.maxit; ++it) {
+            elem_launch(F, OP_KMUL, b.w.dn, b.w.p, b.w.y, 0, cs, &ctl->all_done, nullptr, nullptr, hv.row == nullptr);
+            hipLaunchKernelGGL(k_cg_iter_small, dim3(1), dim3(SMALL_T), 0, cs, b.w, F->mass.as<double>(),
+                               F->pinned.as<uint8_t>(), nv, cm, ck, st, hv, p.tol, p.maxit, ctl);
+        }
+        HIPCHK(hipGetLastError());
+        return;
+    }
     for (int it = 0; it < count && it < p.maxit; ++it) {
         if (list) {
             hipLaunchKernelGGL(k_active, dim3(1), dim3(VT), 0, cs, (const SolveCtl *)ctl, b.tptr, F->tmesh,
