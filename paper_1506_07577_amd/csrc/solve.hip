@@ -58,6 +58,25 @@ __device__ __forceinline__ int chunk_of(const Chunks &ch) {
     return ch.xcd ? (int)xcd_block(blockIdx.x, gridDim.x) : (int)blockIdx.x;
 }
 
+// This workgroup's chunk c, its mesh m, its vertices [lo, hi) and its mesh's chunks [c0, c1).
+// ONE: a single mesh, launched one workgroup per chunk, whose chunk c holds vertices
+// [c VT, min((c + 1) VT, nv)): every field follows from blockIdx without a table read, so the
+// first vector loads do not wait behind a chain of dependent table loads.
+struct ChunkAt {
+    int c, m, c0, c1;
+    int64_t lo, hi;
+};
+template <bool ONE>
+__device__ __forceinline__ ChunkAt chunk_at(const Chunks &ch, int64_t nv) {
+    if (ONE) {
+        const int c = (int)xcd_block(blockIdx.x, gridDim.x);
+        const int64_t lo = (int64_t)c * VT;
+        return ChunkAt{c, 0, 0, (int)gridDim.x, lo, lo + VT < nv ? lo + VT : nv};
+    }
+    const int c = chunk_of(ch), m = ch.mesh[c];
+    return ChunkAt{c, m, ch.cptr[m], ch.cptr[m + 1], ch.lo[c], ch.hi[c]};
+}
+
 static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + VT - 1) / VT)); }
 
 // Sum of one double over a 256-thread block (fixed order).
@@ -377,15 +396,17 @@ __device__ __forceinline__ void finished(const HaloView &h, const double *y, int
 }
 
 // q = Pi (cm M p - ck y); chunk partial p.q (y finished here if the element map left it in the halo)
+template <bool ONE>
 __global__ __launch_bounds__(VT) void k_cg_Ap(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
                                               double cm, double ck, const CGState *st, Chunks ch, HaloView hv,
                                               double *part) {
     __shared__ double s4[4];
-    const int c = chunk_of(ch);
-    if (st[ch.mesh[c]].done) return;   // uniform over the block
-    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    const ChunkAt a = chunk_at<ONE>(ch, nv);
+    const int c = a.c;
+    if (st[a.m].done) return;   // uniform over the block
+    const int64_t v = a.lo + threadIdx.x;
     double pq = 0.0;
-    if (v < ch.hi[c]) {
+    if (v < a.hi) {
         const double m = mass[v];
         const bool pin = pinned[v] != 0;
         double y[3];
@@ -421,15 +442,17 @@ __global__ __launch_bounds__(VT) void k_cg_alpha(CGState *st, const double *part
 }
 
 // x += alpha p; r -= alpha q; z = D^-1 r; chunk partials (r.z, r.r)
+template <bool ONE>
 __global__ __launch_bounds__(VT) void k_cg_update(StepVec w, int64_t nv, const CGState *st, Chunks ch, double *part) {
     __shared__ double s4[4];
-    const int c = chunk_of(ch);
-    const CGState &s = st[ch.mesh[c]];
+    const ChunkAt a = chunk_at<ONE>(ch, nv);
+    const int c = a.c;
+    const CGState &s = st[a.m];
     if (s.done) return;
     const double alpha = s.alpha;
-    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
+    const int64_t v = a.lo + threadIdx.x;
     double rz = 0.0, rr = 0.0;
-    if (v < ch.hi[c]) {
+    if (v < a.hi) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
@@ -473,13 +496,14 @@ __global__ __launch_bounds__(VT) void k_cg_beta(CGState *st, const double *part,
 }
 
 // p = z + beta p
+template <bool ONE>
 __global__ __launch_bounds__(VT) void k_cg_p(StepVec w, int64_t nv, const CGState *st, Chunks ch) {
-    const int c = chunk_of(ch);
-    const CGState &s = st[ch.mesh[c]];
+    const ChunkAt a = chunk_at<ONE>(ch, nv);
+    const CGState &s = st[a.m];
     if (s.done) return;
     const double beta = s.beta;
-    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
-    if (v < ch.hi[c])
+    const int64_t v = a.lo + threadIdx.x;
+    if (v < a.hi)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             const int64_t i = k * nv + v;
@@ -497,13 +521,15 @@ constexpr int FUSE_CHUNKS = 2048;
 
 // alpha = (r.z)_prev / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials (r.z, r.r).
 // The vector loads are issued before the partial sums, so they overlap them.
+template <bool ONE>
 __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGState *st, Chunks ch, double *part,
                                                     int par, SolveCtl *ctl) {
     __shared__ double s12[12];
-    const int c = chunk_of(ch), m = ch.mesh[c];
+    const ChunkAt a = chunk_at<ONE>(ch, nv);
+    const int c = a.c, m = a.m;
     if (st[m].done) return;   // uniform over the block
-    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
-    const bool in = v < ch.hi[c];
+    const int64_t v = a.lo + threadIdx.x;
+    const bool in = v < a.hi;
     double x[3] = {0, 0, 0}, p[3] = {0, 0, 0}, r[3] = {0, 0, 0}, q[3] = {0, 0, 0}, dg[3] = {1, 1, 1};
     if (in)
 #pragma unroll
@@ -516,8 +542,8 @@ __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGSta
             dg[k] = w.diag[i];
         }
     double pq, rz0;
-    sum_parts2(part, ch.cptr[m], ch.cptr[m + 1], PQ, RZ + (par ^ 1), s12, pq, rz0);
-    const bool first = c == ch.cptr[m] && threadIdx.x == 0;
+    sum_parts2(part, a.c0, a.c1, PQ, RZ + (par ^ 1), s12, pq, rz0);
+    const bool first = c == a.c0 && threadIdx.x == 0;
     if (!(pq > 0.0)) {   // breakdown: every workgroup of the mesh sees it and leaves x, r alone
         if (first) {
             st[m].pq = pq;
@@ -554,13 +580,15 @@ __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGSta
 }
 
 // stopping test; beta = (r.z)_new / (r.z)_prev; p = z + beta p
+template <bool ONE>
 __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *st, Chunks ch, const double *part,
                                                int par, double tol, int maxit, SolveCtl *ctl) {
     __shared__ double s12[12];
-    const int c = chunk_of(ch), m = ch.mesh[c];
+    const ChunkAt a = chunk_at<ONE>(ch, nv);
+    const int c = a.c, m = a.m;
     if (st[m].done) return;   // uniform; a mesh marked done by its first chunk needs no new p
-    const int64_t v = (int64_t)ch.lo[c] + threadIdx.x;
-    const bool in = v < ch.hi[c];
+    const int64_t v = a.lo + threadIdx.x;
+    const bool in = v < a.hi;
     double z[3] = {0, 0, 0}, p[3] = {0, 0, 0};
     if (in)
 #pragma unroll
@@ -569,10 +597,10 @@ __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *s
             p[k] = w.p[k * nv + v];
         }
     double rz, rr, rz0;
-    sum_parts3(part, ch.cptr[m], ch.cptr[m + 1], RZ + par, RR, RZ + (par ^ 1), s12, rz, rr, rz0);
+    sum_parts3(part, a.c0, a.c1, RZ + par, RR, RZ + (par ^ 1), s12, rz, rr, rz0);
     const bool conv = sqrt(rr) <= tol * st[m].bnorm || rz == 0.0;
     const double beta = rz / rz0;
-    if (c == ch.cptr[m] && threadIdx.x == 0) {
+    if (c == a.c0 && threadIdx.x == 0) {
         CGState &s = st[m];
         const int it = s.iters + 1;
         s.iters = it;
@@ -917,6 +945,8 @@ void launch_iterations(ebbx_fem_s *F, const ebbx_step_params &p, const SolveBufs
         HIPCHK(hipGetLastError());
         return;
     }
+    // one mesh: the vector kernels take their chunk from blockIdx alone
+    const bool one = b.nm == 1;
     for (int it = 0; it < count && it < p.maxit; ++it) {
         if (list) {
             hipLaunchKernelGGL(k_active, dim3(1), dim3(VT), 0, cs, (const SolveCtl *)ctl, b.tptr, F->tmesh,
@@ -924,19 +954,23 @@ void launch_iterations(ebbx_fem_s *F, const ebbx_step_params &p, const SolveBufs
         }
         elem_launch(F, OP_KMUL, b.w.dn, b.w.p, b.w.y, 0, cs, &ctl->all_done, nullptr,
                     b.nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr, nullptr, act);
-        hipLaunchKernelGGL(k_cg_Ap, dim3(b.nch), dim3(VT), 0, cs, b.w, F->mass.as<double>(), F->pinned.as<uint8_t>(),
-                           nv, cm, ck, (const CGState *)st, b.ch, hv, part);
+        hipLaunchKernelGGL(one ? k_cg_Ap<true> : k_cg_Ap<false>, dim3(b.nch), dim3(VT), 0, cs, b.w,
+                           F->mass.as<double>(), F->pinned.as<uint8_t>(), nv, cm, ck, (const CGState *)st, b.ch, hv,
+                           part);
         if (b.fused) {
             const int par = it & 1;
-            hipLaunchKernelGGL(k_cg_update_f, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st, b.ch, part, par, ctl);
-            hipLaunchKernelGGL(k_cg_p_f, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st, b.ch, (const double *)part, par,
-                               p.tol, p.maxit, ctl);
+            hipLaunchKernelGGL(one ? k_cg_update_f<true> : k_cg_update_f<false>, dim3(b.nch), dim3(VT), 0, cs, b.w,
+                               nv, st, b.ch, part, par, ctl);
+            hipLaunchKernelGGL(one ? k_cg_p_f<true> : k_cg_p_f<false>, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st,
+                               b.ch, (const double *)part, par, p.tol, p.maxit, ctl);
         } else {
             hipLaunchKernelGGL(k_cg_alpha, dim3(b.nm), dim3(VT), 0, cs, st, (const double *)part, b.ch, ctl);
-            hipLaunchKernelGGL(k_cg_update, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, (const CGState *)st, b.ch, part);
+            hipLaunchKernelGGL(one ? k_cg_update<true> : k_cg_update<false>, dim3(b.nch), dim3(VT), 0, cs, b.w, nv,
+                               (const CGState *)st, b.ch, part);
             hipLaunchKernelGGL(k_cg_beta, dim3(b.nm), dim3(VT), 0, cs, st, (const double *)part, b.ch, p.tol, p.maxit,
                                ctl);
-            hipLaunchKernelGGL(k_cg_p, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, (const CGState *)st, b.ch);
+            hipLaunchKernelGGL(one ? k_cg_p<true> : k_cg_p<false>, dim3(b.nch), dim3(VT), 0, cs, b.w, nv,
+                               (const CGState *)st, b.ch);
         }
     }
     HIPCHK(hipGetLastError());
