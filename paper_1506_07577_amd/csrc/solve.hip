@@ -77,6 +77,8 @@ __device__ __forceinline__ ChunkAt chunk_at(const Chunks &ch, int64_t nv) {
     return ChunkAt{c, m, ch.cptr[m], ch.cptr[m + 1], ch.lo[c], ch.hi[c]};
 }
 
+static unsigned grid_one(int nch, int cpw) { return (unsigned)((nch + cpw - 1) / cpw); }
+
 static unsigned grid_for(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(4096, (n + VT - 1) / VT)); }
 
 // Sum of one double over a 256-thread block (fixed order).
@@ -87,6 +89,22 @@ __device__ __forceinline__ double block_sum(double x, double *s4) {
     if ((threadIdx.x & 63) == 0) s4[threadIdx.x >> 6] = x;
     __syncthreads();
     return (s4[0] + s4[1]) + (s4[2] + s4[3]);
+}
+
+// N block sums at once (s: 4 N doubles), each combined exactly as block_sum combines one.
+template <int N>
+__device__ __forceinline__ void block_sums(double (&x)[N], double *s) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] += __shfl_xor(x[i], o, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < N; ++i) s[4 * i + (threadIdx.x >> 6)] = x[i];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) x[i] = (s[4 * i] + s[4 * i + 1]) + (s[4 * i + 2] + s[4 * i + 3]);
 }
 
 // Chunk partials, 4 doubles per chunk: [0] p.q, [1] r.r, [2 + parity] r.z of the
@@ -521,11 +539,10 @@ constexpr int FUSE_CHUNKS = 2048;
 
 // alpha = (r.z)_prev / p.q; x += alpha p; r -= alpha q; z = D^-1 r; partials (r.z, r.r).
 // The vector loads are issued before the partial sums, so they overlap them.
-template <bool ONE>
 __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGState *st, Chunks ch, double *part,
                                                     int par, SolveCtl *ctl) {
     __shared__ double s12[12];
-    const ChunkAt a = chunk_at<ONE>(ch, nv);
+    const ChunkAt a = chunk_at<false>(ch, nv);
     const int c = a.c, m = a.m;
     if (st[m].done) return;   // uniform over the block
     const int64_t v = a.lo + threadIdx.x;
@@ -580,11 +597,10 @@ __global__ __launch_bounds__(VT) void k_cg_update_f(StepVec w, int64_t nv, CGSta
 }
 
 // stopping test; beta = (r.z)_new / (r.z)_prev; p = z + beta p
-template <bool ONE>
 __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *st, Chunks ch, const double *part,
                                                int par, double tol, int maxit, SolveCtl *ctl) {
     __shared__ double s12[12];
-    const ChunkAt a = chunk_at<ONE>(ch, nv);
+    const ChunkAt a = chunk_at<false>(ch, nv);
     const int c = a.c, m = a.m;
     if (st[m].done) return;   // uniform; a mesh marked done by its first chunk needs no new p
     const int64_t v = a.lo + threadIdx.x;
@@ -617,6 +633,164 @@ __global__ __launch_bounds__(VT) void k_cg_p_f(StepVec w, int64_t nv, CGState *s
     if (conv || !in) return;
 #pragma unroll
     for (int k = 0; k < 3; ++k) w.p[k * nv + v] = z[k] + beta * p[k];
+}
+
+// The fused iteration's vector kernels for one mesh, CPW chunks per workgroup: workgroup g
+// (dealt to the XCDs in contiguous ranges) takes chunks [g CPW, (g + 1) CPW), thread t vertex
+// g CPW VT + j VT + t of its chunk j.  These kernels move little data each, so much of their
+// time is fixed cost (dispatch, the partial sums every workgroup forms), which fewer
+// workgroups pay fewer times.  Formulas, chunk partials and sums are those of k_cg_Ap,
+// k_cg_update_f and k_cg_p_f, bit for bit.  Measured (64^3 step, 100 iterations): two chunks
+// per workgroup help the p kernel (about 0.5 us per iteration) and slow the other two (the
+// update with two: +0.6 us, both with two: +3.5 us), whose loads already keep HBM busy.
+constexpr int AP_CPW = 1, UP_CPW = 1, P_CPW = 2;
+
+template <int CPW>
+__global__ __launch_bounds__(VT) void k_cg_Ap_one(StepVec w, const double *mass, const uint8_t *pinned, int64_t nv,
+                                                  int nch, double cm, double ck, const CGState *st, HaloView hv,
+                                                  double *part) {
+    __shared__ double s[4 * CPW];
+    if (st[0].done) return;   // uniform
+    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int64_t v0 = (int64_t)g * CPW * VT + threadIdx.x;
+    double pq[CPW];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        pq[j] = 0.0;
+        const int64_t v = v0 + j * VT;
+        if (v < nv) {
+            const double m = mass[v];
+            const bool pin = pinned[v] != 0;
+            double y[3];
+            finished(hv, w.y, nv, v, y);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int64_t i = k * nv + v;
+                const double p = w.p[i];
+                const double q = pin ? 0.0 : cm * m * p - ck * y[k];
+                w.q[i] = q;
+                pq[j] += p * q;
+            }
+        }
+    }
+    block_sums<CPW>(pq, s);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < CPW; ++j)
+            if (g * CPW + j < nch) part[4 * (g * CPW + j) + PQ] = pq[j];
+}
+
+template <int CPW>
+__global__ __launch_bounds__(VT) void k_cg_update_one(StepVec w, int64_t nv, int nch, CGState *st, double *part,
+                                                      int par, SolveCtl *ctl) {
+    __shared__ double s[8 * CPW > 12 ? 8 * CPW : 12];
+    if (st[0].done) return;   // uniform
+    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int64_t v0 = (int64_t)g * CPW * VT + threadIdx.x;
+    double x[CPW][3], p[CPW][3], r[CPW][3], q[CPW][3], dg[CPW][3];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const int64_t v = v0 + j * VT;
+        const bool in = v < nv;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int64_t i = k * nv + v;
+            x[j][k] = in ? w.x[i] : 0.0;
+            p[j][k] = in ? w.p[i] : 0.0;
+            r[j][k] = in ? w.r[i] : 0.0;
+            q[j][k] = in ? w.q[i] : 0.0;
+            dg[j][k] = in ? w.diag[i] : 1.0;
+        }
+    }
+    double pq, rz0;
+    sum_parts2(part, 0, nch, PQ, RZ + (par ^ 1), s, pq, rz0);
+    const bool first = g == 0 && threadIdx.x == 0;
+    if (!(pq > 0.0)) {   // breakdown: every workgroup sees it and leaves x, r alone
+        if (first) {
+            st[0].pq = pq;
+            st[0].status = EBBX_E_NOT_SPD;
+            mark_done(st[0], ctl, 0);
+        }
+        return;
+    }
+    const double alpha = rz0 / pq;
+    if (first) {
+        st[0].pq = pq;
+        st[0].alpha = alpha;
+    }
+    double red[2 * CPW];   // (r.z, r.r) of chunk j at 2 j, 2 j + 1
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        double rz = 0.0, rr = 0.0;
+        const int64_t v = v0 + j * VT;
+        if (v < nv)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int64_t i = k * nv + v;
+                w.x[i] = x[j][k] + alpha * p[j][k];
+                const double rn = r[j][k] - alpha * q[j][k];
+                const double z = rn / dg[j][k];
+                w.r[i] = rn;
+                w.z[i] = z;
+                rz += rn * z;
+                rr += rn * rn;
+            }
+        red[2 * j] = rz;
+        red[2 * j + 1] = rr;
+    }
+    block_sums<2 * CPW>(red, s);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int j = 0; j < CPW; ++j)
+            if (g * CPW + j < nch) {
+                part[4 * (g * CPW + j) + RZ + par] = red[2 * j];
+                part[4 * (g * CPW + j) + RR] = red[2 * j + 1];
+            }
+}
+
+template <int CPW>
+__global__ __launch_bounds__(VT) void k_cg_p_one(StepVec w, int64_t nv, int nch, CGState *st, const double *part,
+                                                 int par, double tol, int maxit, SolveCtl *ctl) {
+    __shared__ double s12[12];
+    if (st[0].done) return;   // uniform
+    const int g = (int)xcd_block(blockIdx.x, gridDim.x);
+    const int64_t v0 = (int64_t)g * CPW * VT + threadIdx.x;
+    double z[CPW][3], p[CPW][3];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const int64_t v = v0 + j * VT;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            z[j][k] = v < nv ? w.z[k * nv + v] : 0.0;
+            p[j][k] = v < nv ? w.p[k * nv + v] : 0.0;
+        }
+    }
+    double rz, rr, rz0;
+    sum_parts3(part, 0, nch, RZ + par, RR, RZ + (par ^ 1), s12, rz, rr, rz0);
+    const bool conv = sqrt(rr) <= tol * st[0].bnorm || rz == 0.0;
+    const double beta = rz / rz0;
+    if (g == 0 && threadIdx.x == 0) {
+        CGState &s = st[0];
+        const int it = s.iters + 1;
+        s.iters = it;
+        s.rr = rr;
+        if (conv) {
+            s.converged = 1;
+            mark_done(s, ctl, 0);
+        } else {
+            s.beta = beta;
+            s.rz = rz;
+            if (it >= maxit) mark_done(s, ctl, 0);
+        }
+    }
+    if (conv) return;
+#pragma unroll
+    for (int j = 0; j < CPW; ++j) {
+        const int64_t v = v0 + j * VT;
+        if (v < nv)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) w.p[k * nv + v] = z[j][k] + beta * p[j][k];
+    }
 }
 
 // One CG iteration after K p for a single mesh of at most SMALL_NV vertices, in one workgroup:
@@ -954,15 +1128,27 @@ void launch_iterations(ebbx_fem_s *F, const ebbx_step_params &p, const SolveBufs
         }
         elem_launch(F, OP_KMUL, b.w.dn, b.w.p, b.w.y, 0, cs, &ctl->all_done, nullptr,
                     b.nm > 1 ? (const int *)(ctl + 1) : nullptr, hv.row == nullptr, nullptr, act);
+        if (one && b.fused) {
+            // one mesh: the fused iteration's vector kernels with several chunks per workgroup
+            const int par = it & 1;
+            hipLaunchKernelGGL(k_cg_Ap_one<AP_CPW>, dim3(grid_one(b.nch, AP_CPW)), dim3(VT), 0, cs, b.w,
+                               F->mass.as<double>(), F->pinned.as<uint8_t>(), nv, b.nch, cm, ck, (const CGState *)st,
+                               hv, part);
+            hipLaunchKernelGGL(k_cg_update_one<UP_CPW>, dim3(grid_one(b.nch, UP_CPW)), dim3(VT), 0, cs, b.w, nv,
+                               b.nch, st, part, par, ctl);
+            hipLaunchKernelGGL(k_cg_p_one<P_CPW>, dim3(grid_one(b.nch, P_CPW)), dim3(VT), 0, cs, b.w, nv, b.nch, st,
+                               (const double *)part, par, p.tol, p.maxit, ctl);
+            continue;
+        }
         hipLaunchKernelGGL(one ? k_cg_Ap<true> : k_cg_Ap<false>, dim3(b.nch), dim3(VT), 0, cs, b.w,
                            F->mass.as<double>(), F->pinned.as<uint8_t>(), nv, cm, ck, (const CGState *)st, b.ch, hv,
                            part);
         if (b.fused) {
             const int par = it & 1;
-            hipLaunchKernelGGL(one ? k_cg_update_f<true> : k_cg_update_f<false>, dim3(b.nch), dim3(VT), 0, cs, b.w,
-                               nv, st, b.ch, part, par, ctl);
-            hipLaunchKernelGGL(one ? k_cg_p_f<true> : k_cg_p_f<false>, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st,
-                               b.ch, (const double *)part, par, p.tol, p.maxit, ctl);
+            hipLaunchKernelGGL(k_cg_update_f, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st, b.ch, part, par,
+                               ctl);
+            hipLaunchKernelGGL(k_cg_p_f, dim3(b.nch), dim3(VT), 0, cs, b.w, nv, st, b.ch,
+                               (const double *)part, par, p.tol, p.maxit, ctl);
         } else {
             hipLaunchKernelGGL(k_cg_alpha, dim3(b.nm), dim3(VT), 0, cs, st, (const double *)part, b.ch, ctl);
             hipLaunchKernelGGL(one ? k_cg_update<true> : k_cg_update<false>, dim3(b.nch), dim3(VT), 0, cs, b.w, nv,
