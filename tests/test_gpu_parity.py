@@ -335,6 +335,33 @@ def test_step_tolerance_and_iterations(precond, strat):
     mesh.fem.close()
 
 
+@pytest.mark.parametrize("strat", ["seg", "block"])
+def test_step_one_mesh_odd_chunks(strat):
+    """One mesh above the single-workgroup size with an odd number of 256-vertex chunks (17^3
+    cube: 5,832 vertices, 23 chunks, so the p kernel's last two-chunk workgroup holds one chunk
+    and a ragged tail), FP64 neo-Hookean: a step stopped by its tolerance after more iterations
+    than the first captured chunk holds (the oracle takes 41 at 1e-12), then a fixed odd
+    iteration count from that state, each against the oracle."""
+    m = mg.jitter(mg.kuhn_cube(17), 0.01, seed=4)
+    assert m.X.shape[0] == 5832
+    mesh, ref = _pair(m, 1, "f64", strat, E=1e6, nu=0.45, morton=(strat == "block"))
+    d0 = mg.perturbed_state(m, 0.02, seed=10)
+    v0 = 0.1 * mg.direction(m, 11)
+    d, v = mesh.to_dev(d0), mesh.to_dev(v0)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-3, tol=1e-12, maxit=1000))
+    d1, v1, _dv, so = ref.implicit_step(d0, v0, 1e-3, tol=1e-12, maxit=1000)
+    assert so.iters > 32
+    assert s.status == ebbx.OK and abs(s.iters - so.iters) <= 1 and s.iters < 1000
+    assert s.rel_res <= 1e-12
+    assert nerr(mesh.from_dev(v), v1) <= 1e-9 and nerr(mesh.from_dev(d), d1) <= 1e-9
+    dh, vh = mesh.from_dev(d), mesh.from_dev(v)
+    s = ebbx.stats_fetch(mesh.fem.implicit_step(d, v, 1e-3, tol=0.0, maxit=37))
+    d2, v2, _dv, so = ref.implicit_step(dh, vh, 1e-3, tol=0.0, maxit=37)
+    assert s.status == ebbx.OK and s.iters == so.iters == 37
+    assert nerr(mesh.from_dev(v), v2) <= 1e-10 and nerr(mesh.from_dev(d), d2) <= 1e-10
+    mesh.fem.close()
+
+
 def test_step_error_conditions():
     m = mg.kuhn_cube(3)
     # maxit reached with a tolerance: NOT_CONVERGED, iterate kept
